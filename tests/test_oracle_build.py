@@ -1,0 +1,241 @@
+"""Pins of the oracle's construction and query (Sections 3.1-3.4): the
+bijection onto [0, n), brute-force injectivity of the slots on tiny inputs,
+the remap's definition, the two remap encodings agreeing, determinism, the
+failure paths and the paper's construction claim at lambda = 4."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_15539_amd import keygen as K
+
+L = O.lib()
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_space.json")))
+C = 0x517CC1B727220A95
+M64 = (1 << 64) - 1
+
+
+def is_perm(out, n):
+    return np.array_equal(np.sort(out), np.arange(n, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 10, 100, 1000, 4097, 100_000, 1_000_000])
+def test_bijection(n):
+    keys = K.u64_keys(n)
+    m = O.build_u64(keys)
+    assert is_perm(O.query_u64(m, keys), n)
+    assert is_perm(O.query_u64(m, K.query_stream(n)), n)
+
+
+def slots_bigint(m, keys):
+    """Slots from eq. partbucket and eq. slot in exact integer arithmetic."""
+    p = m.params
+    P, S, B, seed = p.num_parts, p.slots_per_part, p.buckets_per_part, p.seed
+    out = []
+    for k in keys:
+        h = (C * int(k)) & M64
+        part, x = (P * h) >> 64, (P * h) & M64
+        x2 = (x * x) >> 64
+        x3 = (x2 * x) >> 64
+        y = (x2 >> 1) + (x3 >> 1)
+        g = y - (y >> 8) + (x >> 8)
+        b = part * B + ((B * g) >> 64)
+        hp = (C * (int(m.pilots[b]) ^ seed)) & M64
+        out.append(part * S + (((C * (h ^ hp)) >> 64) & (S - 1)))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 5, 50, 300, 2000])
+def test_bruteforce_injective_many_seeds(n):
+    for seed in range(12):
+        keys = K.u64_keys(n, seed=1000 + seed)
+        m = O.build_u64(keys, seed=seed)
+        slots = slots_bigint(m, keys)
+        assert len(set(slots)) == n
+        assert max(slots) < m.params.num_parts * m.params.slots_per_part
+        assert is_perm(O.query_u64(m, keys), n)
+
+
+def test_remap_definition():
+    """F[q_i - n] = L_i for the taken slots q_i >= n and the free slots
+    L_i < n in order; other entries repeat their predecessor."""
+    n = 20_000
+    keys = K.u64_keys(n, seed=77)
+    m = O.build_u64(keys)
+    p = m.params
+    slots = np.array(O.query_u64(m, keys, O.REMAP_NONE), dtype=np.int64)
+    taken = np.zeros(p.num_parts * p.slots_per_part, dtype=bool)
+    taken[slots] = True
+    assert taken.sum() == n
+    q = np.nonzero(taken[n:])[0]
+    gaps = np.nonzero(~taken[:n])[0]
+    assert len(q) == len(gaps)
+    F = m.F.astype(np.int64)
+    assert np.array_equal(F[q], gaps)
+    prev = 0
+    for t in range(len(F)):
+        if not taken[n + t]:
+            assert F[t] == prev
+        prev = F[t]
+    assert np.all(np.diff(F) >= 0)
+
+
+@pytest.mark.parametrize("n", [1000, 123_457, 1_000_000])
+def test_clef_and_plain_remap_agree(n):
+    keys = K.u64_keys(n, seed=3)
+    m = O.build_u64(keys)
+    probe = np.concatenate([keys, K.nonmember_keys(50_000)])
+    a = O.query_u64(m, probe, O.REMAP_CLEF)
+    b = O.query_u64(m, probe, O.REMAP_PLAIN)
+    assert np.array_equal(a, b)
+    assert a.max() < n
+    s = O.query_u64(m, probe, O.REMAP_NONE)
+    assert np.array_equal(a[s < n], s[s < n])
+
+
+def test_nonmembers_in_range():
+    n = 50_000
+    m = O.build_u64(K.u64_keys(n))
+    out = O.query_u64(m, K.nonmember_keys(200_000))
+    assert out.max() < n
+
+
+def test_deterministic():
+    keys = K.u64_keys(200_000, seed=9)
+    a, b = O.build_u64(keys), O.build_u64(keys)
+    assert np.array_equal(a.pilots, b.pilots) and np.array_equal(a.clef, b.clef)
+    assert a.params.seed == b.params.seed
+
+
+def test_duplicate_keys_rejected():
+    keys = K.u64_keys(1000)
+    keys[500] = keys[17]
+    with pytest.raises(O.BuildError) as e:
+        O.build_u64(keys)
+    assert e.value.code == O.EDUPLICATE
+
+
+def test_part_overflow():
+    """All keys hashed into part 0 of 2: more than S keys in one part."""
+    cinv = pow(C, -1, 1 << 64)
+    rng = np.random.default_rng(1)
+    hs = [int(x) for x in rng.integers(0, 1 << 62, size=200, dtype=np.uint64)]
+    keys = np.array([(h * cinv) & M64 for h in hs], dtype=np.uint64)
+    p = O.params_explicit(200, 2, 7, 60)  # S = 128 < 200 keys in part 0
+    with pytest.raises(O.BuildError) as e:
+        O.build_u64(keys, params=p)
+    assert e.value.code == O.EPART_OVERFLOW
+
+
+def test_eviction_cap_forces_reseed_then_failure():
+    keys = K.u64_keys(1_000_000)
+    with pytest.raises(O.BuildError) as e:
+        O.build_u64(keys, eviction_factor=0, max_attempts=2)
+    assert e.value.code == O.EBUILD_FAILED
+
+
+def test_reseed_recovers():
+    """With a tight cap some attempts fail; a later seed succeeds."""
+    keys = K.u64_keys(30_000, seed=4)
+    for factor in (0, 1):
+        try:
+            m = O.build_u64(keys, eviction_factor=factor, max_attempts=64)
+        except O.BuildError:
+            continue
+        assert is_perm(O.query_u64(m, keys), len(keys))
+        assert m.params.seed == m.stats.attempts - 1
+        return
+    pytest.skip("no attempt succeeded under the tight cap")
+
+
+def test_strings_bijection_and_remaps():
+    data, off = K.strings(30_000, seed=11)
+    m = O.build_bytes(data, off)
+    out = O.query_bytes(m, data, off)
+    assert is_perm(out, 30_000)
+    assert np.array_equal(out, O.query_bytes(m, data, off, O.REMAP_PLAIN))
+
+
+def test_duplicate_strings_rejected():
+    data, off = K.strings(100, seed=2)
+    s = data[off[3]:off[4]].tobytes()
+    strs = [data[off[i]:off[i + 1]].tobytes() for i in range(100)] + [s]
+    buf = np.frombuffer(b"".join(strs) + b"\0" * 64, dtype=np.uint8)
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in strs])]).astype(np.uint64)
+    with pytest.raises(O.BuildError) as e:
+        O.build_bytes(buf, offs)
+    assert e.value.code == O.EDUPLICATE
+
+
+def test_space_of_built_mphf():
+    """A built MPHF at Default params takes the accounted bits/key."""
+    n = 1_000_000
+    m = O.build_u64(K.u64_keys(n))
+    bits = 8 * (m.pilots.size + m.clef.size) / n
+    p = m.params
+    assert m.pilots.size == p.num_parts * p.buckets_per_part
+    assert abs(bits - 2.94) < 0.01  # 4 parts of 2^18 slots, remap at load 0.954
+
+
+def test_worked_example_conventions():
+    """Fig. 1: P = 2, B = 5, n = 23: a key in the second part with local
+    bucket 1 uses pilot index 6; its slot 25 >= n is remapped below n."""
+    g = GOLD["fig_overview"]
+    p = O.params_explicit(g["n"], g["P"], 4, g["B"])  # S = 16
+    S = p.slots_per_part
+    # a hash in part 1 whose relative position gives local bucket 1
+    found = None
+    for t in range(1 << 16):
+        h = (1 << 63) + t * (1 << 47)
+        if L.orc_part(p, h) == 1 and L.orc_bucket(p, h) - g["B"] == 1:
+            found = h
+            break
+    assert found is not None
+    assert L.orc_bucket(p, found) == g["bucket_of_part1_key"]
+    # slot 25 is local slot 9 of part 1: a pilot mapping the key there is remapped
+    local = g["slot_of_part1_key"] - S
+    for pl in range(256):
+        if L.orc_slot(p, found, pl) == g["slot_of_part1_key"]:
+            assert L.orc_reduce(found ^ L.orc_hp(0, pl), S) == local
+            break
+    keys = K.u64_keys(g["n"], seed=5)
+    m = O.build_u64(keys, params=p)
+    out = O.query_u64(m, keys)
+    slots = O.query_u64(m, keys, O.REMAP_NONE)
+    assert is_perm(out, g["n"])
+    assert (slots >= g["n"]).any() and out.max() < g["n"]
+
+
+def lambda4_params(gamma):
+    S = 1 << 18
+    n = int(0.99 * S)
+    return O.params_explicit(n, 1, 18, math.ceil(0.99 * S / 4.0), gamma=gamma), n
+
+
+def test_lambda4_cubic_builds():
+    """Fig. bucket-fn-plot: at lambda = 4.0, S = 2^18, alpha = 0.99 the cubic
+    gamma_3 builds with few evictions."""
+    p, n = lambda4_params(O.GAMMA_CUBIC)
+    m = O.build_u64(K.u64_keys(n, seed=7), params=p, max_attempts=1)
+    assert m.stats.evictions < 1 * p.slots_per_part
+    assert abs(8 * m.pilots.size / n - 2.0) < 0.01  # "2.0 bits/key for the pilots"
+
+
+def test_lambda4_linear_fails_quick():
+    """Same setting, linear gamma_1: evictions pass S (the paper's cap is
+    10*S; the full cap runs in the slow test below), where gamma_3 above
+    needs under S."""
+    p, n = lambda4_params(O.GAMMA_LINEAR)
+    with pytest.raises(O.BuildError) as e:
+        O.build_u64(K.u64_keys(n, seed=7), params=p, eviction_factor=1, max_attempts=1)
+    assert e.value.code == O.EBUILD_FAILED
+
+
+@pytest.mark.slow
+def test_lambda4_linear_fails_full_cap():
+    p, n = lambda4_params(O.GAMMA_LINEAR)
+    with pytest.raises(O.BuildError):
+        O.build_u64(K.u64_keys(n, seed=7), params=p, eviction_factor=10, max_attempts=1)
