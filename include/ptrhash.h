@@ -1,0 +1,209 @@
+/*
+ * ptrhash.h -- C ABI of the MI355X (gfx950) PtrHash query library.
+ *
+ * PtrHash (R. Groot Koerkamp, "PtrHash: Minimal Perfect Hashing at RAM
+ * Throughput", SEA 2025, arXiv 2502.15539) maps a set of n keys bijectively
+ * onto [0, n). A key is hashed (Section 3.1, "Hash functions"), sent to a
+ * part and a bucket (eq. partbucket, Section 3.3), the bucket's 8-bit pilot
+ * picks a slot (eq. slot), and slots >= n are remapped into the free slots
+ * below n through one CacheLineEF table (Section 3.4). This library evaluates
+ * that function on large batches of keys with HIP kernels; it also holds a
+ * host-side construction (Section 3.2) so that a caller can build the
+ * pilots and the remap table it loads.
+ *
+ * Conventions of every entry point:
+ *  - Return value: PTRHASH_OK (0) or a ptrhash_status code; nothing throws
+ *    across the ABI. ptrhash_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Pointers documented as "device" are HIP device allocations (for
+ *    example torch CUDA tensors); "host" pointers are ordinary memory.
+ *    The caller owns every buffer it passes; the library owns only the
+ *    device copies it makes in ptrhash_load.
+ *  - Queries are asynchronous on the caller's stream: arguments are checked
+ *    on the host before the launch; a fault inside a kernel surfaces at the
+ *    caller's next synchronisation of that stream.
+ */
+#ifndef PTRHASH_H
+#define PTRHASH_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PTRHASH_API __attribute__((visibility("default")))
+
+typedef enum ptrhash_status {
+    PTRHASH_OK = 0,
+    PTRHASH_E_INVAL = 1,       /* null pointer, bad size, inconsistent params */
+    PTRHASH_E_STATE = 2,       /* handle not loaded, or wrong key kind */
+    PTRHASH_E_RANGE = 3,       /* 32-bit output with n > 2^32, size limits */
+    PTRHASH_E_NOMEM = 4,       /* device or host allocation failed */
+    PTRHASH_E_HIP = 5,         /* a HIP runtime call failed */
+    PTRHASH_E_DUPLICATE = 6,   /* construction: two equal keys */
+    PTRHASH_E_BUILD = 7,       /* construction: every seed attempt failed */
+    PTRHASH_E_REMAP_RANGE = 8  /* construction: a CacheLineEF line overflows */
+} ptrhash_status;
+
+/* Bucket assignment function (Section 3.3). */
+enum { PTRHASH_GAMMA_CUBIC = 0, PTRHASH_GAMMA_LINEAR = 1 };
+/* Remap encoding for slots >= n (Section 3.4): CacheLineEF lines, a plain
+ * u32 array, or none (a non-minimal perfect hash that returns the slot). */
+enum { PTRHASH_REMAP_CLEF = 0, PTRHASH_REMAP_U32 = 1, PTRHASH_REMAP_NONE = 2 };
+/* Key type: 64-bit integers or byte strings (Section 3.1). */
+enum { PTRHASH_KEY_U64 = 0, PTRHASH_KEY_BYTES = 1 };
+/* Parameter presets (Section 4.1.2, "Recommended parameters"). */
+enum { PTRHASH_PRESET_DEFAULT = 0, PTRHASH_PRESET_FAST = 1, PTRHASH_PRESET_COMPACT = 2 };
+
+/*
+ * Parameters of one MPHF. num_parts = P, slots per part S = 2^log2_slots,
+ * buckets_per_part = B (Section 3.1). seed enters the pilot hash
+ * h_p(p) = C*(p xor seed) and, for byte keys, the string hash.
+ * remap_len must equal P*S - n. index_bits (32 or 64) is the width of each
+ * output index. Passed by pointer and copied.
+ */
+typedef struct ptrhash_params {
+    uint64_t n;
+    uint64_t num_parts;
+    uint32_t log2_slots;
+    uint32_t buckets_per_part;
+    uint64_t seed;
+    uint32_t gamma;       /* PTRHASH_GAMMA_* */
+    uint32_t remap_kind;  /* PTRHASH_REMAP_* */
+    uint64_t remap_len;   /* P*S - n */
+    uint32_t key_kind;    /* PTRHASH_KEY_* */
+    uint32_t index_bits;  /* 32 or 64 */
+} ptrhash_params;
+
+typedef struct ptrhash_handle ptrhash_handle;
+
+/* Create an empty handle (*out). Host only; no device memory yet. */
+PTRHASH_API int ptrhash_create(ptrhash_handle **out);
+
+/* Free the handle and its device buffers. NULL is a no-op. The caller must
+ * not destroy a handle while queries on it are still running. */
+PTRHASH_API int ptrhash_destroy(ptrhash_handle *h);
+
+/*
+ * Parameters by the paper's rule (Section 3.1, "Parameter values"):
+ * alpha*S >= 80000*ln(n/80000) keys per part (at least 80000), S a power of
+ * two, P = ceil(n/(alpha*S)), B = ceil(alpha*S/lambda); a single part
+ * shrinks S to the smallest power of two >= n/alpha. Presets: Default
+ * (cubic, lambda 3.5, CacheLineEF), Fast (linear, lambda 3.0, u32 remap),
+ * Compact (cubic, lambda 4.0, CacheLineEF), alpha = 0.99 for all.
+ * index_bits 0 picks 32 when n <= 2^32, else 64.
+ */
+PTRHASH_API int ptrhash_params_default(uint64_t n, int preset, uint32_t key_kind, uint32_t index_bits,
+                                       uint64_t seed, ptrhash_params *out);
+
+/* Bytes of the remap table for these params: CacheLineEF
+ * ceil(remap_len/44)*64, u32 4*remap_len, none 0. */
+PTRHASH_API uint64_t ptrhash_remap_bytes(const ptrhash_params *params);
+
+/*
+ * Copy an MPHF into handle-owned device memory: pilots (host, P*B bytes,
+ * indexed by global bucket part*B + bucket) and remap (host,
+ * ptrhash_remap_bytes(params) bytes; may be NULL when that is 0). Remap
+ * layout, CacheLineEF: one 64-byte line per 44 entries; bytes [0,4) the
+ * 32-bit offset, [4,20) the 128-bit high-part bitmap as two little-endian
+ * u64 words, [20,64) the 44 low bytes (Section 3.4, eq. clef). Synchronous.
+ * A reload replaces the previous MPHF. Errors: E_INVAL (null pointer, S not
+ * a power of two, P*S < n, B == 0, remap_len != P*S - n, bad enum),
+ * E_RANGE (index_bits 32 with n > 2^32, P*B or P*S >= 2^40), E_NOMEM, E_HIP.
+ */
+PTRHASH_API int ptrhash_load(ptrhash_handle *h, const uint8_t *pilots, const void *remap,
+                             const ptrhash_params *params);
+
+/* The parameters of the loaded MPHF (E_STATE if none). */
+PTRHASH_API int ptrhash_get_params(const ptrhash_handle *h, ptrhash_params *out);
+
+/*
+ * Evaluate the MPHF on n_q u64 keys: out[i] = H(keys[i]) (eq. partbucket,
+ * eq. slot, remap of Section 3.4). keys: device, n_q u64. out: device, n_q
+ * elements of index_bits. Members map bijectively onto [0, n); any other key
+ * gets a deterministic value in [0, n) (minimal remaps) or [0, P*S) (no
+ * remap). Asynchronous on stream; keys/out must stay valid until it
+ * completes and must not overlap. n_q == 0 launches nothing. Errors:
+ * E_STATE (not loaded, or a byte-key MPHF), E_INVAL (null), E_HIP.
+ */
+PTRHASH_API int ptrhash_query(ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, void *out,
+                              hipStream_t stream);
+
+/*
+ * As ptrhash_query for byte-string keys: key i is data[offsets[i] ..
+ * offsets[i+1]). data: device, 8-byte aligned, with at least 64 readable
+ * bytes after offsets[n_q]; offsets: device, n_q+1 u64, non-decreasing.
+ * Errors: E_STATE (not loaded, or a u64-key MPHF), E_INVAL.
+ */
+PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, const uint64_t *offsets,
+                                    uint64_t n_q, void *out, hipStream_t stream);
+
+/* Kernel choice for a handle's queries: kernel 0 = one key per lane,
+ * 1 = keys_per_lane keys per lane with every pilot load issued before the
+ * first is used; block = threads per workgroup (64..1024, multiple of 64).
+ * keys_per_lane in {1, 2, 4, 8, 16}. Errors: E_INVAL. */
+enum { PTRHASH_KERNEL_PLAIN = 0, PTRHASH_KERNEL_PIPELINED = 1 };
+PTRHASH_API int ptrhash_set_kernel(ptrhash_handle *h, int kernel, int keys_per_lane, int block);
+
+/* Message of the calling thread's last failure ("" if none). */
+PTRHASH_API const char *ptrhash_last_error(void);
+
+/* ---- Construction (host; Section 3.2, Section 3.4) ---- */
+
+typedef struct ptrhash_build_info {
+    uint64_t attempts;        /* seeds tried */
+    uint64_t evictions;       /* total over parts, final attempt */
+    uint64_t max_part_evictions;
+    uint64_t max_bucket_size;
+} ptrhash_build_info;
+
+/*
+ * Build an MPHF on n distinct u64 keys (host memory) with hash-evict pilot
+ * search: buckets largest first, the smallest free pilot in [0, 256), else
+ * evict the buckets of the pilot with the least sum of squared sizes of
+ * colliding buckets, never one of the 16 most recently placed; a part fails
+ * after 10*S evictions and the whole build retries with seed+1 (at most 16
+ * seeds). params: in/out (a retry stores the seed used). pilots: host,
+ * P*B bytes. remap: host, ptrhash_remap_bytes(params) bytes. threads: worker
+ * threads (0 = all cores). info may be NULL. Errors: E_INVAL, E_DUPLICATE,
+ * E_BUILD (a part over S keys, or all seeds failed), E_REMAP_RANGE, E_NOMEM.
+ */
+PTRHASH_API int ptrhash_build_u64(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
+                                  void *remap, int threads, ptrhash_build_info *info);
+
+/* As ptrhash_build_u64 for byte strings data[offsets[i] .. offsets[i+1])
+ * (host memory); equal 64-bit hashes of distinct strings cause a reseed. */
+PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+                                    ptrhash_params *params, uint8_t *pilots, void *remap, int threads,
+                                    ptrhash_build_info *info);
+
+/* ---- Roofline microbenchmarks (device; the denominators of the metric) ----
+ * gather: out[i] = keys[i] xor table[hi(keys[i] * table_len)] -- stream a
+ * key in, one random byte from a table_len-byte table, stream a u64 out;
+ * the memory pattern of a query without its arithmetic. copy: out[i] =
+ * keys[i]. Both asynchronous on stream; keys_per_lane/block as in
+ * ptrhash_set_kernel. */
+PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const uint8_t *table,
+                                     uint64_t table_len, uint64_t *out, int keys_per_lane, int block,
+                                     hipStream_t stream);
+PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane,
+                                   int block, hipStream_t stream);
+
+/* ---- Synthetic inputs (device; for benchmarks and tests) ----
+ * Key i of a key set = SplitMix64 output i of the stream seeded seed
+ * (distinct for distinct i). gen_u64_keys writes keys start..start+count-1.
+ * gen_query_stream writes members of the n-key set in a seeded shuffled
+ * order: entry i is key pi(i), pi a 4-round Feistel bijection of [0, n) with
+ * cycle walking keyed by order_seed. Asynchronous on stream. */
+PTRHASH_API int ptrhash_gen_u64_keys(uint64_t seed, uint64_t start, uint64_t count, uint64_t *out,
+                                     hipStream_t stream);
+PTRHASH_API int ptrhash_gen_query_stream(uint64_t n, uint64_t key_seed, uint64_t order_seed, uint64_t start,
+                                         uint64_t count, uint64_t *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

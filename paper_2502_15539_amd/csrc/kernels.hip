@@ -1,0 +1,205 @@
+// Query kernels for gfx950 and their launchers.
+//
+// The query of one key is: stream the key in, hash it, find its part and
+// bucket, gather the bucket's 8-bit pilot from a table that is usually far
+// larger than the L2 caches, compute the slot, decode the remap line for the
+// rare slot >= n, stream the index out (Appendix A describes the same
+// pipeline on a CPU with software prefetching; here the latency of the
+// random pilot gathers is hidden by many independent loads in flight per
+// wavefront instead).
+//
+//  - query_plain: one key per lane, the straightforward form.
+//  - query_pipelined<K>: K keys per lane in a tile of K*blockDim keys; all
+//    K key loads, then all K pilot gathers, are issued before any result is
+//    used, and the remap lines of the K keys are fetched together in one
+//    round trip. Keys and indices are streamed with non-temporal loads and
+//    stores so that they do not evict pilots from the L2 and MALL.
+//  - query_bytes<K>: the same for packed byte-string keys.
+#include "internal.h"
+#include "mphf_device.h"
+
+namespace ptrhash {
+
+template <typename T>
+__device__ __forceinline__ T nt_load(const T *p) { return __builtin_nontemporal_load(p); }
+
+template <typename OutT>
+__device__ __forceinline__ void nt_store(OutT v, OutT *p) { __builtin_nontemporal_store(v, p); }
+
+template <typename OutT>
+__global__ void __launch_bounds__(1024) query_plain(const uint64_t *__restrict__ keys, uint64_t nq,
+                                                    OutT *__restrict__ out, DevMphf m) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const uint64_t h = hash_u64(keys[i]);
+    uint32_t part;
+    const uint64_t b = bucket_of(m, h, part);
+    uint64_t v = slot_of(m, h, part, m.pilots[b]);
+    if (m.remap_kind != kRemapNone && v >= m.n) v = remap_lookup(m, v);
+    out[i] = (OutT)v;
+}
+
+// Slots of K keys (already hashed) -> indices, with the remap loads of all
+// K keys issued before any is decoded.
+template <int K>
+__device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], const bool (&ok)[K]) {
+    if (m.remap_kind == kRemapNone) return;
+    bool need[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) need[j] = ok[j] && v[j] >= m.n;
+    if (m.remap_kind == kRemapU32) {
+        const uint32_t *R = reinterpret_cast<const uint32_t *>(m.remap);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (need[j]) v[j] = R[v[j] - m.n];
+        return;
+    }
+    ClefRead r[K];
+    uint32_t idx[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (need[j]) {
+            uint64_t line;
+            clef_index(v[j] - m.n, line, idx[j]);
+            r[j] = clef_load(m.remap, line, idx[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (need[j]) v[j] = clef_value(r[j], idx[j]);
+}
+
+template <int K, typename OutT>
+__global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restrict__ keys, uint64_t nq,
+                                                        OutT *__restrict__ out, DevMphf m) {
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+    const uint32_t stride = blockDim.x;
+    uint64_t h[K];
+    bool ok[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * stride;
+        ok[j] = i < nq;
+        h[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
+    }
+    uint32_t part[K], pil[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t b = bucket_of(m, h[j], part[j]);
+        pil[j] = ok[j] ? m.pilots[b] : 0;
+    }
+    uint64_t v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = slot_of(m, h[j], part[j], pil[j]);
+    finish_k<K>(m, v, ok);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * stride;
+        if (ok[j]) nt_store((OutT)v[j], out + i);
+    }
+}
+
+template <int K, typename OutT>
+__global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict__ data,
+                                                      const uint64_t *__restrict__ offsets, uint64_t nq,
+                                                      OutT *__restrict__ out, DevMphf m) {
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+    const uint32_t stride = blockDim.x;
+    uint64_t h[K];
+    bool ok[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * stride;
+        ok[j] = i < nq;
+        if (ok[j]) {
+            const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+            h[j] = hash_bytes(m.seed, data, o0, o1 - o0);
+        } else {
+            h[j] = 0;
+        }
+    }
+    uint32_t part[K], pil[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t b = bucket_of(m, h[j], part[j]);
+        pil[j] = ok[j] ? m.pilots[b] : 0;
+    }
+    uint64_t v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = slot_of(m, h[j], part[j], pil[j]);
+    finish_k<K>(m, v, ok);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * stride;
+        if (ok[j]) nt_store((OutT)v[j], out + i);
+    }
+}
+
+// ---- launchers ----
+
+static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+template <typename OutT>
+static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, const Tuning &t,
+                               hipStream_t s) {
+    OutT *o = static_cast<OutT *>(out);
+    const uint32_t blk = (uint32_t)t.block;
+    if (t.kernel == kKernelPlain) {
+        hipLaunchKernelGGL(query_plain<OutT>, dim3((uint32_t)ceil_div(nq, blk)), dim3(blk), 0, s, keys, nq, o, m);
+        return hipGetLastError();
+    }
+    const uint64_t grid = ceil_div(nq, (uint64_t)blk * t.keys_per_lane);
+    switch (t.keys_per_lane) {
+#define PTRHASH_CASE(KK)                                                                                     \
+    case KK:                                                                                                 \
+        hipLaunchKernelGGL((query_pipelined<KK, OutT>), dim3((uint32_t)grid), dim3(blk), 0, s, keys, nq, o, m); \
+        break;
+        PTRHASH_CASE(1)
+        PTRHASH_CASE(2)
+        PTRHASH_CASE(4)
+        PTRHASH_CASE(8)
+        PTRHASH_CASE(16)
+#undef PTRHASH_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
+                            const Tuning &t, hipStream_t s) {
+    return out64 ? launch_u64_t<uint64_t>(m, keys, nq, out, t, s) : launch_u64_t<uint32_t>(m, keys, nq, out, t, s);
+}
+
+template <typename OutT>
+static hipError_t launch_bytes_t(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
+                                 void *out, const Tuning &t, hipStream_t s) {
+    OutT *o = static_cast<OutT *>(out);
+    const uint32_t blk = (uint32_t)t.block;
+    const int K = t.kernel == kKernelPlain ? 1 : t.keys_per_lane;
+    const uint64_t grid = ceil_div(nq, (uint64_t)blk * K);
+    switch (K) {
+#define PTRHASH_CASE(KK)                                                                                   \
+    case KK:                                                                                               \
+        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), dim3((uint32_t)grid), dim3(blk), 0, s, data, offsets, nq, \
+                           o, m);                                                                          \
+        break;
+        PTRHASH_CASE(1)
+        PTRHASH_CASE(2)
+        PTRHASH_CASE(4)
+        PTRHASH_CASE(8)
+        PTRHASH_CASE(16)
+#undef PTRHASH_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
+                              void *out, bool out64, const Tuning &t, hipStream_t s) {
+    return out64 ? launch_bytes_t<uint64_t>(m, data, offsets, nq, out, t, s)
+                 : launch_bytes_t<uint32_t>(m, data, offsets, nq, out, t, s);
+}
+
+}  // namespace ptrhash

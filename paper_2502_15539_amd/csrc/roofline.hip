@@ -1,0 +1,79 @@
+// Roofline microbenchmarks: the memory pattern of a query with none of its
+// arithmetic. gather: stream a u64 key in, read one byte at a random index
+// hi(key * T) of a T-byte table, stream a u64 out. copy: stream in, stream
+// out. Same tiling, non-temporal streams and keys-per-lane knob as the
+// pipelined query kernel, so a query's time can be compared with these.
+#include "internal.h"
+
+namespace ptrhash {
+
+template <int K>
+__global__ void __launch_bounds__(1024) bench_gather_k(const uint64_t *__restrict__ keys, uint64_t nq,
+                                                       const uint8_t *__restrict__ table, uint64_t T,
+                                                       uint64_t *__restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+    uint64_t k[K];
+    bool ok[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * blockDim.x;
+        ok[j] = i < nq;
+        k[j] = ok[j] ? __builtin_nontemporal_load(keys + i) : 0;
+    }
+    uint32_t b[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) b[j] = ok[j] ? table[__umul64hi(k[j], T)] : 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * blockDim.x;
+        if (ok[j]) __builtin_nontemporal_store(k[j] ^ b[j], out + i);
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(1024) bench_copy_k(const uint64_t *__restrict__ keys, uint64_t nq,
+                                                     uint64_t *__restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+    uint64_t k[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * blockDim.x;
+        k[j] = i < nq ? __builtin_nontemporal_load(keys + i) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint64_t i = base + (uint64_t)j * blockDim.x;
+        if (i < nq) __builtin_nontemporal_store(k[j], out + i);
+    }
+}
+
+static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t T, uint64_t *out,
+                               int K, int block, hipStream_t s) {
+    const dim3 grid((uint32_t)ceil_div(nq, (uint64_t)block * K)), blk((uint32_t)block);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(bench_gather_k<1>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    case 2: hipLaunchKernelGGL(bench_gather_k<2>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    case 4: hipLaunchKernelGGL(bench_gather_k<4>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    case 8: hipLaunchKernelGGL(bench_gather_k<8>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    case 16: hipLaunchKernelGGL(bench_gather_k<16>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bench_copy(const uint64_t *keys, uint64_t nq, uint64_t *out, int K, int block, hipStream_t s) {
+    const dim3 grid((uint32_t)ceil_div(nq, (uint64_t)block * K)), blk((uint32_t)block);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(bench_copy_k<1>, grid, blk, 0, s, keys, nq, out); break;
+    case 2: hipLaunchKernelGGL(bench_copy_k<2>, grid, blk, 0, s, keys, nq, out); break;
+    case 4: hipLaunchKernelGGL(bench_copy_k<4>, grid, blk, 0, s, keys, nq, out); break;
+    case 8: hipLaunchKernelGGL(bench_copy_k<8>, grid, blk, 0, s, keys, nq, out); break;
+    case 16: hipLaunchKernelGGL(bench_copy_k<16>, grid, blk, 0, s, keys, nq, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ptrhash

@@ -1,0 +1,265 @@
+"""Python binding of the C ABI in include/ptrhash.h (argument marshalling only).
+
+Every query runs in the HIP kernels of ``libptrhash_hip.so``; there is no
+fallback. If the library is missing, :func:`lib` raises. Torch is used only
+to hold device memory and to name the stream a launch goes on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libptrhash_hip.so")
+
+OK, E_INVAL, E_STATE, E_RANGE, E_NOMEM, E_HIP, E_DUPLICATE, E_BUILD, E_REMAP_RANGE = range(9)
+GAMMA_CUBIC, GAMMA_LINEAR = 0, 1
+REMAP_CLEF, REMAP_U32, REMAP_NONE = 0, 1, 2
+KEY_U64, KEY_BYTES = 0, 1
+PRESET_DEFAULT, PRESET_FAST, PRESET_COMPACT = 0, 1, 2
+KERNEL_PLAIN, KERNEL_PIPELINED = 0, 1
+
+
+class PtrHashError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint64),
+        ("num_parts", C.c_uint64),
+        ("log2_slots", C.c_uint32),
+        ("buckets_per_part", C.c_uint32),
+        ("seed", C.c_uint64),
+        ("gamma", C.c_uint32),
+        ("remap_kind", C.c_uint32),
+        ("remap_len", C.c_uint64),
+        ("key_kind", C.c_uint32),
+        ("index_bits", C.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    def copy(self) -> "Params":
+        return Params.from_buffer_copy(self)
+
+
+class BuildInfo(C.Structure):
+    _fields_ = [
+        ("attempts", C.c_uint64),
+        ("evictions", C.c_uint64),
+        ("max_part_evictions", C.c_uint64),
+        ("max_bucket_size", C.c_uint64),
+    ]
+
+
+_lib = None
+_SIGS = {
+    "ptrhash_create": (C.c_int, [C.POINTER(C.c_void_p)]),
+    "ptrhash_destroy": (C.c_int, [C.c_void_p]),
+    "ptrhash_params_default": (C.c_int, [C.c_uint64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(Params)]),
+    "ptrhash_remap_bytes": (C.c_uint64, [C.POINTER(Params)]),
+    "ptrhash_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Params)]),
+    "ptrhash_get_params": (C.c_int, [C.c_void_p, C.POINTER(Params)]),
+    "ptrhash_query": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "ptrhash_query_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "ptrhash_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "ptrhash_last_error": (C.c_char_p, []),
+    "ptrhash_build_u64": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_int,
+                                    C.POINTER(BuildInfo)]),
+    "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                      C.c_int, C.POINTER(BuildInfo)]),
+    "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
+                                       C.c_void_p]),
+    "ptrhash_bench_copy": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "ptrhash_gen_u64_keys": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "ptrhash_gen_query_stream": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p,
+                                           C.c_void_p]),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_15539_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise PtrHashError(rc, where, lib().ptrhash_last_error().decode())
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None and a.size else None
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    """A HIP stream handle: explicit int, a torch stream, or torch's current one."""
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def params_default(n: int, preset: int = PRESET_DEFAULT, key_kind: int = KEY_U64, index_bits: int = 0,
+                   seed: int = 0) -> Params:
+    p = Params()
+    _check(lib().ptrhash_params_default(int(n), int(preset), int(key_kind), int(index_bits), int(seed), C.byref(p)),
+           "ptrhash_params_default")
+    return p
+
+
+def remap_bytes(p: Params) -> int:
+    return int(lib().ptrhash_remap_bytes(C.byref(p)))
+
+
+@dataclass
+class Built:
+    """Host arrays of a built MPHF, ready for :meth:`Mphf.load`."""
+
+    params: Params
+    pilots: np.ndarray
+    remap: np.ndarray
+    info: BuildInfo
+
+    @property
+    def bits_per_key(self) -> float:
+        return 8.0 * (self.pilots.size + self.remap.size) / self.params.n
+
+
+def build_u64(keys: np.ndarray, params: Params | None = None, threads: int = 0, **kw) -> Built:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    p = (params if params is not None else params_default(len(keys), **kw)).copy()
+    pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    remap = np.zeros(remap_bytes(p), dtype=np.uint8)
+    info = BuildInfo()
+    _check(lib().ptrhash_build_u64(_np_ptr(keys), len(keys), C.byref(p), _np_ptr(pilots), _np_ptr(remap),
+                                   int(threads), C.byref(info)), "ptrhash_build_u64")
+    return Built(p, pilots, remap, info)
+
+
+def build_bytes(data: np.ndarray, offsets: np.ndarray, params: Params | None = None, threads: int = 0,
+                **kw) -> Built:
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = len(offsets) - 1
+    p = (params if params is not None else params_default(n, key_kind=KEY_BYTES, **kw)).copy()
+    pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    remap = np.zeros(remap_bytes(p), dtype=np.uint8)
+    info = BuildInfo()
+    _check(lib().ptrhash_build_bytes(_np_ptr(data), _np_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
+                                     _np_ptr(remap), int(threads), C.byref(info)), "ptrhash_build_bytes")
+    return Built(p, pilots, remap, info)
+
+
+class Mphf:
+    """A device-resident MPHF behind one library handle."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().ptrhash_create(C.byref(h)), "ptrhash_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().ptrhash_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load(self, params: Params, pilots: np.ndarray, remap: np.ndarray | None) -> "Mphf":
+        pilots = np.ascontiguousarray(pilots, dtype=np.uint8)
+        remap = None if remap is None else np.ascontiguousarray(remap, dtype=np.uint8)
+        _check(lib().ptrhash_load(self._h, _np_ptr(pilots), _np_ptr(remap), C.byref(params)), "ptrhash_load")
+        return self
+
+    @classmethod
+    def from_built(cls, b: Built) -> "Mphf":
+        return cls().load(b.params, b.pilots, b.remap)
+
+    @property
+    def params(self) -> Params:
+        p = Params()
+        _check(lib().ptrhash_get_params(self._h, C.byref(p)), "ptrhash_get_params")
+        return p
+
+    def set_kernel(self, kernel: int, keys_per_lane: int = 4, block: int = 256):
+        _check(lib().ptrhash_set_kernel(self._h, int(kernel), int(keys_per_lane), int(block)), "ptrhash_set_kernel")
+
+    def query_into(self, keys, out, stream=None):
+        """keys: cuda uint64 tensor; out: cuda tensor of index_bits width."""
+        n = keys.numel()
+        _check(lib().ptrhash_query(self._h, _dev_ptr(keys), n, _dev_ptr(out), _stream(stream)), "ptrhash_query")
+        return out
+
+    def query(self, keys, stream=None):
+        import torch
+
+        dt = torch.int64 if self.params.index_bits == 64 else torch.int32
+        out = torch.empty(keys.numel(), dtype=dt, device=keys.device)
+        return self.query_into(keys, out, stream)
+
+    def query_bytes_into(self, data, offsets, out, stream=None):
+        n = offsets.numel() - 1
+        _check(lib().ptrhash_query_bytes(self._h, _dev_ptr(data), _dev_ptr(offsets), n, _dev_ptr(out),
+                                         _stream(stream)), "ptrhash_query_bytes")
+        return out
+
+    def query_bytes(self, data, offsets, stream=None):
+        import torch
+
+        dt = torch.int64 if self.params.index_bits == 64 else torch.int32
+        out = torch.empty(offsets.numel() - 1, dtype=dt, device=offsets.device)
+        return self.query_bytes_into(data, offsets, out, stream)
+
+
+def bench_gather(keys, table, out, keys_per_lane=4, block=256, stream=None):
+    _check(lib().ptrhash_bench_gather(_dev_ptr(keys), keys.numel(), _dev_ptr(table), table.numel(), _dev_ptr(out),
+                                      int(keys_per_lane), int(block), _stream(stream)), "ptrhash_bench_gather")
+
+
+def bench_copy(keys, out, keys_per_lane=4, block=256, stream=None):
+    _check(lib().ptrhash_bench_copy(_dev_ptr(keys), keys.numel(), _dev_ptr(out), int(keys_per_lane), int(block),
+                                    _stream(stream)), "ptrhash_bench_copy")
+
+
+def gen_u64_keys(out, seed, start=0, stream=None):
+    """Fill the cuda uint64 tensor ``out`` with keys start.. of the key set."""
+    _check(lib().ptrhash_gen_u64_keys(int(seed), int(start), out.numel(), _dev_ptr(out), _stream(stream)),
+           "ptrhash_gen_u64_keys")
+    return out
+
+
+def gen_query_stream(out, n, key_seed, order_seed, start=0, stream=None):
+    """Fill ``out`` with entries start.. of the shuffled member stream of the n-key set."""
+    _check(lib().ptrhash_gen_query_stream(int(n), int(key_seed), int(order_seed), int(start), out.numel(),
+                                          _dev_ptr(out), _stream(stream)), "ptrhash_gen_query_stream")
+    return out

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP kernels against the oracle, element by element.
+
+Every MPHF here is built by the oracle; the same parameters, pilots and
+remap bytes are loaded into the library, and the GPU indices must equal the
+oracle's query bit for bit, for members and non-members, every kernel
+variant, both output widths and every remap encoding. At the full
+benchmark sizes, where the oracle cannot build, the library's own build is
+checked by properties that hold at any size (bijection of the members, range
+of non-members, agreement of the kernel variants).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_15539_amd import keygen as K
+from paper_2502_15539_amd import ptrhash as P
+
+from .mphf_pairs import ORACLE_REMAP, load
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+VARIANTS = [(P.KERNEL_PLAIN, 1, 256), (P.KERNEL_PLAIN, 1, 64), (P.KERNEL_PIPELINED, 1, 256),
+            (P.KERNEL_PIPELINED, 2, 128), (P.KERNEL_PIPELINED, 4, 256), (P.KERNEL_PIPELINED, 8, 256),
+            (P.KERNEL_PIPELINED, 16, 64), (P.KERNEL_PIPELINED, 4, 1024)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_cache = {}
+
+
+def oracle_mphf(n, seed=0, **kw):
+    key = (n, seed, tuple(sorted(kw.items())))
+    if key not in _cache:
+        keys = K.u64_keys(n, seed=100 + seed)
+        _cache[key] = (keys, O.build_u64(keys, seed=seed, **kw))
+    return _cache[key]
+
+
+def probe_keys(keys, extra=20_000, seed=0):
+    rng = np.random.default_rng(seed)
+    members = keys[rng.permutation(len(keys))]
+    return np.concatenate([members, K.nonmember_keys(extra, seed=seed + 77)])
+
+
+def gpu_query(mphf, q, index_bits):
+    qt = torch.from_numpy(q.view(np.int64)).to(DEV)
+    out = mphf.query(qt)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    return o.view(np.uint64) if index_bits == 64 else o.view(np.uint32).astype(np.uint64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 1000, 65_537, 1_000_000])
+def test_u64_all_variants_clef(n):
+    keys, m = oracle_mphf(n)
+    q = probe_keys(keys)
+    want = O.query_u64(m, q, O.REMAP_CLEF)
+    for bits in (32, 64):
+        g = load(m, P.REMAP_CLEF, bits)
+        for kern, kpl, blk in VARIANTS:
+            say(f"[parity] n={n} bits={bits} kernel={kern} kpl={kpl} block={blk} nq={len(q)}")
+            g.set_kernel(kern, kpl, blk)
+            got = gpu_query(g, q, bits)
+            mism = np.nonzero(got != want)[0]
+            assert mism.size == 0, f"{mism.size} mismatches, first at {mism[:5]}: {got[mism[:5]]} vs {want[mism[:5]]}"
+
+
+@pytest.mark.parametrize("remap", [P.REMAP_U32, P.REMAP_NONE])
+@pytest.mark.parametrize("n", [1000, 300_001])
+def test_u64_other_remaps(n, remap):
+    keys, m = oracle_mphf(n)
+    q = probe_keys(keys)
+    want = O.query_u64(m, q, ORACLE_REMAP[remap])
+    g = load(m, remap, 64)
+    for kern, kpl, blk in VARIANTS[:1] + VARIANTS[4:6]:
+        say(f"[parity] remap={remap} n={n} kernel={kern} kpl={kpl}")
+        g.set_kernel(kern, kpl, blk)
+        assert np.array_equal(gpu_query(g, q, 64), want)
+
+
+@pytest.mark.parametrize("lam,gamma", [(3.0, O.GAMMA_LINEAR), (4.0, O.GAMMA_CUBIC)])
+def test_u64_fast_and_compact(lam, gamma):
+    keys, m = oracle_mphf(200_000, lam=lam, gamma=gamma)
+    q = probe_keys(keys)
+    for remap in (P.REMAP_CLEF, P.REMAP_U32):
+        want = O.query_u64(m, q, ORACLE_REMAP[remap])
+        g = load(m, remap, 32)
+        say(f"[parity] lambda={lam} gamma={gamma} remap={remap}")
+        assert np.array_equal(gpu_query(g, q, 32), want)
+
+
+def test_u64_reseeded_mphf():
+    """An MPHF whose construction needed a new seed queries with that seed."""
+    n = 20_000
+    keys = K.u64_keys(n, seed=4)
+    try:
+        m = O.build_u64(keys, params=O.params_explicit(n, 1, 15, 5000, seed=0))
+    except O.BuildError:
+        pytest.skip("oracle could not build this instance")
+    g = load(m, P.REMAP_CLEF, 32)
+    q = probe_keys(keys)
+    say(f"[parity] reseeded seed={m.params.seed}")
+    assert np.array_equal(gpu_query(g, q, 32), O.query_u64(m, q))
+
+
+@pytest.mark.parametrize("n", [1, 5, 30_000, 200_003])
+def test_bytes_parity(n):
+    data, off = K.strings(n, seed=31)
+    m = O.build_bytes(data, off)
+    qd, qo = K.string_query_stream(n, seed=31)
+    want = O.query_bytes(m, qd, qo)
+    assert np.array_equal(np.sort(want), np.arange(n, dtype=np.uint64))
+    g = load(m, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES)
+    dt = torch.from_numpy(qd).to(DEV)
+    ot = torch.from_numpy(qo.view(np.int64)).to(DEV)
+    for kern, kpl, blk in VARIANTS:
+        say(f"[parity-bytes] n={n} kernel={kern} kpl={kpl} block={blk}")
+        g.set_kernel(kern, kpl, blk)
+        got = g.query_bytes(dt, ot)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().view(np.uint32).astype(np.uint64)
+        assert np.array_equal(got, want)
+
+
+def test_bytes_unaligned_and_edge_lengths():
+    """Lengths 0..40 at every byte alignment (the kernel reads aligned words
+    and shifts), hashed the same as the oracle."""
+    strs = [bytes([65 + (i * 7 + j) % 26 for j in range(L)]) for i, L in enumerate(list(range(41)) * 3)]
+    strs = list(dict.fromkeys(strs))
+    buf = b"".join(strs)
+    data = np.frombuffer(buf + b"\0" * 64, dtype=np.uint8)
+    off = np.concatenate([[0], np.cumsum([len(s) for s in strs])]).astype(np.uint64)
+    m = O.build_bytes(data, off)
+    want = O.query_bytes(m, data, off)
+    g = load(m, P.REMAP_CLEF, 64, key_kind=P.KEY_BYTES)
+    say(f"[parity-bytes] edge lengths n={len(strs)}")
+    got = g.query_bytes(torch.from_numpy(data).to(DEV), torch.from_numpy(off.view(np.int64)).to(DEV))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint64), want)
+
+
+def test_empty_query_and_errors():
+    keys, m = oracle_mphf(1000)
+    g = load(m, P.REMAP_CLEF, 32)
+    empty = torch.empty(0, dtype=torch.int64, device=DEV)
+    out = torch.empty(0, dtype=torch.int32, device=DEV)
+    g.query_into(empty, out)  # no launch
+    with pytest.raises(P.PtrHashError) as e:
+        g.query_bytes(torch.zeros(8, dtype=torch.uint8, device=DEV), torch.zeros(2, dtype=torch.int64, device=DEV))
+    assert e.value.code == P.E_STATE
+    torch.cuda.synchronize()
+
+
+def test_device_generators_match_host():
+    n = 1_000_003
+    say("[gen] device generators vs host")
+    k = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
+    q = P.gen_query_stream(torch.empty(n, dtype=torch.int64, device=DEV), n, K.KEY_SEED, K.ORDER_SEED)
+    torch.cuda.synchronize()
+    assert np.array_equal(k.cpu().numpy().view(np.uint64), K.u64_keys(n))
+    assert np.array_equal(q.cpu().numpy().view(np.uint64), K.query_stream(n))
+    part = P.gen_query_stream(torch.empty(1000, dtype=torch.int64, device=DEV), n, K.KEY_SEED, K.ORDER_SEED,
+                              start=5000)
+    torch.cuda.synchronize()
+    assert np.array_equal(part.cpu().numpy().view(np.uint64), K.query_stream(n, start=5000, count=1000))
+
+
+def bijection_on_device(out, n):
+    seen = torch.zeros(n, dtype=torch.bool, device=out.device)
+    assert int(out.min()) >= 0 and int(out.max()) < n
+    seen[out.long()] = True
+    return bool(seen.all())
+
+
+@pytest.mark.parametrize("n", [10**8])
+def test_full_size_properties(n):
+    """Library-built MPHF at the 10^8-key workload: all members map
+    bijectively onto [0, n), every kernel variant agrees, non-members stay
+    below n."""
+    say(f"[full] n={n}: host keys + library build")
+    keys = K.u64_keys(n)
+    b = P.build_u64(keys, index_bits=32)
+    del keys
+    g = P.Mphf.from_built(b)
+    q = P.gen_query_stream(torch.empty(n, dtype=torch.int64, device=DEV), n, K.KEY_SEED, K.ORDER_SEED)
+    ref = None
+    for kern, kpl, blk in [(P.KERNEL_PLAIN, 1, 256), (P.KERNEL_PIPELINED, 4, 256), (P.KERNEL_PIPELINED, 8, 512)]:
+        say(f"[full] n={n} kernel={kern} kpl={kpl} block={blk}")
+        g.set_kernel(kern, kpl, blk)
+        out = g.query(q)
+        torch.cuda.synchronize()
+        if ref is None:
+            assert bijection_on_device(out, n)
+            ref = out
+        else:
+            assert torch.equal(out, ref)
+    nm = torch.from_numpy(K.nonmember_keys(1_000_000).view(np.int64)).to(DEV)
+    o = g.query(nm)
+    torch.cuda.synchronize()
+    assert int(o.long().max()) < n
