@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="u64_1e9", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", help="auto | plain | K,BLOCK (pipelined)")
+    ap.add_argument("--gather", default="auto", help="auto | K,BLOCK for the gather roofline kernel")
     ap.add_argument("--cpu-sample", type=int, default=50_000_000, help="oracle sample size (keys); 0 = skip")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the build (0 = all, max 16)")
     return ap.parse_args()
@@ -161,9 +162,11 @@ def main():
     table = torch.randint(0, 256, (p.num_parts * p.buckets_per_part,), dtype=torch.uint8, device=dev)
     gout = torch.empty(n, dtype=torch.int64, device=dev)
     gsweep = {}
-    for k in (1, 2, 4, 8, 16):
-        for b in (128, 256, 512):
-            gsweep[(k, b)] = time_launches(torch, lambda: P.bench_gather(q, table, gout, k, b), 3, 1)
+    gcands = [(k, b) for k in (1, 2, 4, 8, 16) for b in (128, 256, 512)]
+    if args.gather != "auto":
+        gcands = [tuple(int(x) for x in args.gather.split(","))]
+    for k, b in gcands:
+        gsweep[(k, b)] = time_launches(torch, lambda: P.bench_gather(q, table, gout, k, b), 3, 1)
     gbest = min(gsweep, key=gsweep.get)
     gather_ms = gsweep[gbest]
     csweep = {}
