@@ -9,6 +9,8 @@ shuffled stream of all 10^9 members resident in HBM, u64 indices out.
 Prints ONE JSON line with queries/s, ns/key, the fraction of a measured
 random-gather roofline (the same memory pattern with no hashing), the HBM
 roofline of the query kernel, and the CPU oracle timed on a bounded sample.
+Other workloads (--workload): the 10^8 and 10^6 u64 sets, 3*10^8 byte
+strings, and the 64-MPHF serving workload.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "queries/s (ns/key) at n=1e9 u64 keys; % of random-gather HBM roofline"
 
 WORKLOADS = {
     # name: (n, key kind, index bits, description)
@@ -34,6 +37,12 @@ WORKLOADS = {
                                   "Default params"),
     "u64_1e6": (10**6, "u64", 32, "n=1e6 distinct uniform u64 keys, shuffled stream of all members, u32 indices, "
                                   "Default params"),
+    "bytes_3e8": (3 * 10**8, "bytes", 32, "n=3e8 distinct random byte strings, length uniform 10-50 over printable "
+                                          "ASCII, packed with u64 offsets; shuffled stream of all members, u32 "
+                                          "indices, Default params"),
+    "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params; "
+                                 "Poisson arrivals of batches log-uniform in [1, 65536] keys, each against one "
+                                 "MPHF; continuous batching"),
 }
 
 
@@ -51,6 +60,7 @@ def parse():
     ap.add_argument("--gather", default="auto", help="auto | K,BLOCK for the gather roofline kernel")
     ap.add_argument("--cpu-sample", type=int, default=50_000_000, help="oracle sample size (keys); 0 = skip")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the build (0 = all, max 16)")
+    ap.add_argument("--requests", type=int, default=20000, help="serving workload: requests per run")
     return ap.parse_args()
 
 
@@ -66,6 +76,219 @@ def time_launches(torch, fn, steps, warmup):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps  # ms
+
+
+def kernel_candidates(P, spec, bytes_keys=False):
+    if spec == "plain":
+        return [(P.KERNEL_PLAIN, 1, 256)]
+    if spec != "auto":
+        kk, bb = (int(x) for x in spec.split(","))
+        return [(P.KERNEL_PIPELINED, kk, bb)]
+    ks = (1, 2, 4, 8) if bytes_keys else (1, 2, 4, 8, 16)
+    return [(P.KERNEL_PLAIN, 1, 256)] + [(P.KERNEL_PIPELINED, k, b) for k in ks for b in (128, 256, 512)]
+
+
+def tune_and_time(torch, P, mphf, run, args, bytes_keys=False):
+    """Sweep the kernel choice, then time exactly args.steps launches."""
+    sweep = {}
+    for c in kernel_candidates(P, args.kernel, bytes_keys):
+        mphf.set_kernel(*c)
+        sweep[c] = time_launches(torch, run, 3, 1)
+    best = min(sweep, key=sweep.get)
+    mphf.set_kernel(*best)
+    log("[bench] sweep: " + ", ".join(f"{c[0]}/{c[1]}/{c[2]}={v:.3f}ms" for c, v in sorted(sweep.items())))
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        run()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return best, sweep, ev0.elapsed_time(ev1) / args.steps, wall
+
+
+def bijective(torch, out, n):
+    seen = torch.zeros(n, dtype=torch.bool, device=out.device)
+    o64 = out.long()
+    ok = int(o64.min()) >= 0 and int(o64.max()) < n
+    seen[o64] = True
+    return bool(ok and seen.all())
+
+
+def kernel_name(P, best):
+    return "plain" if best[0] == P.KERNEL_PLAIN else f"pipelined(keys_per_lane={best[1]},block={best[2]})"
+
+
+def record(args, n, ms, wall, desc, extra_config, dtype, per_key, **fields):
+    achieved = per_key * n / (ms / 1e3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": n / (ms / 1e3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded SplitMix64 keys, Feistel-shuffled member stream)",
+        "config": {"workload": desc, "n": n, **extra_config, "parallelism": "single GPU"},
+        "ns_per_key": ms * 1e6 / n,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_key": per_key},
+        "timed_wall_s": wall,
+    }
+    rec.update(fields)
+    return rec
+
+
+def remap_fraction(torch, P, params, pilots, queries=None, data=None, offsets=None):
+    """Fraction of member queries whose slot is >= n (non-minimal view of the same pilots)."""
+    phf = P.Mphf()
+    pp = params.copy()
+    pp.remap_kind = P.REMAP_NONE
+    pp.index_bits = 64
+    phf.load(pp, pilots, None)
+    slots = phf.query(queries) if queries is not None else phf.query_bytes(data, offsets)
+    frac = float((slots >= params.n).sum().item()) / params.n
+    phf.close()
+    return frac
+
+
+def run_u64(args, torch, K, P):
+    n, _, bits, desc = WORKLOADS[args.workload]
+    dev = "cuda"
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    keys = K.u64_keys(n)
+    t1 = time.time()
+    built = P.build_u64(keys, index_bits=bits, threads=threads)
+    t2 = time.time()
+    del keys
+    p = built.params
+    log(f"[bench] keygen {t1 - t0:.1f}s build {t2 - t1:.1f}s  P={p.num_parts} S=2^{p.log2_slots} "
+        f"B={p.buckets_per_part} bits/key={built.bits_per_key:.3f} evictions={built.info.evictions}")
+    mphf = P.Mphf.from_built(built)
+
+    q = torch.empty(n, dtype=torch.int64, device=dev)
+    P.gen_query_stream(q, n, K.KEY_SEED, K.ORDER_SEED)
+    out = torch.empty(n, dtype=torch.int64 if bits == 64 else torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_into(q, out), args)
+    bij = bijective(torch, out, n)
+    rfrac = remap_fraction(torch, P, p, built.pilots, queries=q)
+
+    # roofline microbenchmarks on the same key stream
+    table = torch.randint(0, 256, (p.num_parts * p.buckets_per_part,), dtype=torch.uint8, device=dev)
+    gout = torch.empty(n, dtype=torch.int64, device=dev)
+    gcands = [(k, b) for k in (1, 2, 4, 8, 16) for b in (128, 256, 512)]
+    if args.gather != "auto":
+        gcands = [tuple(int(x) for x in args.gather.split(","))]
+    gsweep = {c: time_launches(torch, lambda: P.bench_gather(q, table, gout, c[0], c[1]), 3, 1) for c in gcands}
+    gbest = min(gsweep, key=gsweep.get)
+    gather_ms = gsweep[gbest]
+    copy_ms = min(time_launches(torch, lambda: P.bench_copy(q, gout, k, 256), 3, 1) for k in (1, 4, 8))
+    del gout, table
+    log(f"[bench] query {ms:.3f} ms  gather-roofline {gather_ms:.3f} ms {gbest}  copy {copy_ms:.3f} ms  "
+        f"bijective={bij} remap_frac={rfrac:.5f}")
+
+    cpu = None
+    if args.cpu_sample:
+        from oracle import oracle as O
+
+        ns = min(args.cpu_sample, n)
+        qs = q[:ns].cpu().numpy().view(np.uint64)
+        op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+        m = O.Mphf(op, built.pilots, None, built.remap, None)
+        c0 = time.perf_counter()
+        res = O.query_u64(m, qs, O.REMAP_CLEF)
+        cdt = time.perf_counter() - c0
+        go = out[:ns].cpu().numpy()
+        go = go.view(np.uint64) if bits == 64 else go.view(np.uint32).astype(np.uint64)
+        cpu = {"value": ns / cdt, "unit": "queries/s", "cores": 1, "kind": "oracle", "ns_per_key": cdt / ns * 1e9,
+               "sample": f"first {ns} queries of the same shuffled stream on the same MPHF, single-threaded plain "
+                         f"loop of the C oracle", "matches_gpu": bool(np.array_equal(res, go))}
+        log(f"[bench] cpu oracle {cdt:.1f}s for {ns} keys ({cdt / ns * 1e9:.1f} ns/key) "
+            f"matches_gpu={cpu['matches_gpu']}")
+
+    per_key = 8 + bits // 8 + 1 + rfrac * 64
+    rec = record(args, n, ms, wall, desc,
+                 {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
+                  "log2_slots": p.log2_slots, "buckets_per_part": p.buckets_per_part,
+                  "bits_per_key": round(built.bits_per_key, 4)},
+                 "u64", per_key,
+                 pct_gather_roofline=100.0 * gather_ms / ms,
+                 gather_roofline={"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
+                                  "block": gbest[1], "table_bytes": p.num_parts * p.buckets_per_part},
+                 stream_copy_ms=copy_ms,
+                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256)),
+                 cpu_baseline=cpu,
+                 parity={"bijective_members": bij, "remap_fraction": rfrac},
+                 build_s=t2 - t1,
+                 paper_cpu_context_ns_per_key={"loop": 12, "stream": 8, "default_clef_loop": 21.0,
+                                               "default_clef_stream": 8.7})
+    if args.workload != "u64_1e9":
+        rec["metric"] = f"queries/s (ns/key) at n={n:.0e} u64 keys"
+    return rec, bij
+
+
+def run_bytes(args, torch, K, P):
+    n, _, bits, desc = WORKLOADS[args.workload]
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    d_data, d_off = P.gen_strings(n, K.KEY_SEED)
+    data = d_data.cpu().numpy()
+    offsets = d_off.cpu().numpy().view(np.uint64)
+    del d_data, d_off
+    t1 = time.time()
+    built = P.build_bytes(data, offsets, index_bits=bits, threads=threads)
+    t2 = time.time()
+    total_bytes = int(offsets[-1])
+    del data, offsets
+    p = built.params
+    log(f"[bench] strings {t1 - t0:.1f}s ({total_bytes / n:.1f} B/key) build {t2 - t1:.1f}s P={p.num_parts} "
+        f"bits/key={built.bits_per_key:.3f} seed={p.seed}")
+    mphf = P.Mphf.from_built(built)
+    qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_bytes_into(qd, qo, out), args,
+                                          bytes_keys=True)
+    bij = bijective(torch, out, n)
+    rfrac = remap_fraction(torch, P, p, built.pilots, data=qd, offsets=qo)
+    per_key = total_bytes / n + 8 + 4 + 1 + rfrac * 64
+    log(f"[bench] query {ms:.3f} ms bijective={bij}")
+    rec = record(args, n, ms, wall, desc,
+                 {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
+                  "bits_per_key": round(built.bits_per_key, 4), "mean_key_bytes": total_bytes / n},
+                 "u64", per_key,
+                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256)),
+                 parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
+                 paper_cpu_context_ns_per_key={"default_clef_loop": 37, "default_clef_stream": 23})
+    rec["metric"] = "queries/s (ns/key) at n=3e8 byte-string keys"
+    return rec, bij
+
+
+def run_serve(args, torch, K, P):
+    from paper_2502_15539_amd import serving
+
+    res = serving.run_c5(torch, n_requests=args.requests, threads=args.threads or min(16, os.cpu_count() or 1),
+                         log=log)
+    sat = res["saturated"]
+    rec = {"metric": "serving: queries/s with p50/p99 latency, 64 resident MPHFs", "value": sat["keys_per_s"],
+           "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sat["makespan_s"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic (seeded SplitMix64 keys, log-uniform sizes, Poisson arrivals)",
+           "config": {"workload": WORKLOADS["serve_c5"][3], "requests": args.requests, "parallelism": "single GPU"},
+           "serving": res}
+    return rec, res["served_equals_plain"]
 
 
 def main():
@@ -85,159 +308,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     P.lib()  # fail loudly if the HIP library is missing
-    dev = "cuda"
-    n, kind, bits, desc = WORKLOADS[args.workload]
-    threads = args.threads or min(16, os.cpu_count() or 1)
-
-    # ---- build (host, not timed as part of the metric) ----
-    t0 = time.time()
-    keys = K.u64_keys(n)
-    t1 = time.time()
-    built = P.build_u64(keys, index_bits=bits, threads=threads)
-    t2 = time.time()
-    del keys
-    p = built.params
-    log(f"[bench] keygen {t1 - t0:.1f}s build {t2 - t1:.1f}s  P={p.num_parts} S=2^{p.log2_slots} "
-        f"B={p.buckets_per_part} bits/key={built.bits_per_key:.3f} evictions={built.info.evictions}")
-    mphf = P.Mphf.from_built(built)
-
-    # ---- inputs resident in HBM ----
-    q = torch.empty(n, dtype=torch.int64, device=dev)
-    P.gen_query_stream(q, n, K.KEY_SEED, K.ORDER_SEED)
-    out = torch.empty(n, dtype=torch.int64 if bits == 64 else torch.int32, device=dev)
-    torch.cuda.synchronize()
-
-    # ---- kernel choice (autotuned over keys/lane and block) ----
-    cands = [(P.KERNEL_PLAIN, 1, 256)] + [(P.KERNEL_PIPELINED, k, b) for k in (1, 2, 4, 8, 16)
-                                         for b in (128, 256, 512)]
-    if args.kernel == "plain":
-        cands = [(P.KERNEL_PLAIN, 1, 256)]
-    elif args.kernel != "auto":
-        kk, bb = (int(x) for x in args.kernel.split(","))
-        cands = [(P.KERNEL_PIPELINED, kk, bb)]
-    sweep = {}
-    for c in cands:
-        mphf.set_kernel(*c)
-        sweep[c] = time_launches(torch, lambda: mphf.query_into(q, out), 3, 1)
-    best = min(sweep, key=sweep.get)
-    plain_ms = sweep.get((P.KERNEL_PLAIN, 1, 256))
-    mphf.set_kernel(*best)
-    log(f"[bench] sweep: " + ", ".join(f"{c[0]}/{c[1]}/{c[2]}={v:.2f}ms" for c, v in sorted(sweep.items())))
-
-    # ---- timed steps: one launch each, barrier-free single GPU ----
-    for _ in range(args.warmup):
-        mphf.query_into(q, out)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        mphf.query_into(q, out)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1) / args.steps
-
-    # ---- full-size check: members map bijectively onto [0, n) ----
-    seen = torch.zeros(n, dtype=torch.bool, device=dev)
-    o64 = out.long()
-    in_range = int(o64.min()) >= 0 and int(o64.max()) < n
-    seen[o64] = True
-    bijective = bool(in_range and seen.all())
-    del seen, o64
-
-    # remapped fraction of member queries (slots >= n), from a PHF view of the same pilots
-    phf = P.Mphf()
-    pp = p.copy()
-    pp.remap_kind = P.REMAP_NONE
-    pp.index_bits = 64
-    phf.load(pp, built.pilots, None)
-    slots = phf.query(q)
-    remap_frac = float((slots >= n).sum().item()) / n
-    del slots
-    phf.close()
-    torch.cuda.synchronize()
-
-    # ---- roofline microbenchmarks on the same key stream ----
-    table = torch.randint(0, 256, (p.num_parts * p.buckets_per_part,), dtype=torch.uint8, device=dev)
-    gout = torch.empty(n, dtype=torch.int64, device=dev)
-    gsweep = {}
-    gcands = [(k, b) for k in (1, 2, 4, 8, 16) for b in (128, 256, 512)]
-    if args.gather != "auto":
-        gcands = [tuple(int(x) for x in args.gather.split(","))]
-    for k, b in gcands:
-        gsweep[(k, b)] = time_launches(torch, lambda: P.bench_gather(q, table, gout, k, b), 3, 1)
-    gbest = min(gsweep, key=gsweep.get)
-    gather_ms = gsweep[gbest]
-    csweep = {}
-    for k in (1, 4, 8):
-        csweep[k] = time_launches(torch, lambda: P.bench_copy(q, gout, k, 256), 3, 1)
-    copy_ms = min(csweep.values())
-    del gout, table
-    log(f"[bench] query {ms:.3f} ms  gather-roofline {gather_ms:.3f} ms {gbest}  copy {copy_ms:.3f} ms  "
-        f"bijective={bijective} remap_frac={remap_frac:.5f}")
-
-    # ---- CPU baseline: the oracle's query loop on a bounded sample ----
-    cpu = None
-    if args.cpu_sample:
-        from oracle import oracle as O
-
-        ns = min(args.cpu_sample, n)
-        qs = q[:ns].cpu().numpy().view(np.uint64)
-        op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
-        m = O.Mphf(op, built.pilots, None, built.remap, None)
-        c0 = time.perf_counter()
-        res = O.query_u64(m, qs, O.REMAP_CLEF)
-        cdt = time.perf_counter() - c0
-        agree = bool(np.array_equal(res, out[:ns].cpu().numpy().view(np.uint64) if bits == 64
-                                    else out[:ns].cpu().numpy().view(np.uint32).astype(np.uint64)))
-        cpu = {"value": ns / cdt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "ns_per_key": cdt / ns * 1e9,
-               "sample": f"first {ns} queries of the same shuffled stream on the same MPHF, single-threaded "
-                         f"plain loop of the C oracle",
-               "matches_gpu": agree}
-        log(f"[bench] cpu oracle {cdt:.1f}s for {ns} keys ({cdt / ns * 1e9:.1f} ns/key) matches_gpu={agree}")
-
-    # ---- report ----
-    out_bytes = bits // 8
-    per_key = 8 + out_bytes + 1 + remap_frac * 64
-    achieved = per_key * n / (ms / 1e3) / 1e9
-    qps = n / (ms / 1e3)
-    kern_name = "plain" if best[0] == P.KERNEL_PLAIN else f"pipelined(keys_per_lane={best[1]},block={best[2]})"
-    rec = {
-        "metric": "queries/s (ns/key) at n=1e9 u64 keys; % of random-gather HBM roofline",
-        "value": qps,
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic (seeded SplitMix64 keys, Feistel-shuffled member stream)",
-        "config": {"workload": desc, "n": n, "kernel": kern_name, "index_bits": bits,
-                   "num_parts": p.num_parts, "log2_slots": p.log2_slots, "buckets_per_part": p.buckets_per_part,
-                   "bits_per_key": round(built.bits_per_key, 4), "parallelism": "single GPU"},
-        "ns_per_key": ms * 1e6 / n,
-        "pct_gather_roofline": 100.0 * gather_ms / ms,
-        "gather_roofline": {"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
-                            "block": gbest[1], "table_bytes": p.num_parts * p.buckets_per_part},
-        "stream_copy_ms": copy_ms,
-        "plain_kernel_ms": plain_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_key": per_key},
-        "cpu_baseline": cpu,
-        "parity": {"bijective_members": bijective, "remap_fraction": remap_frac},
-        "build_s": t2 - t1,
-        "timed_wall_s": wall,
-        "paper_cpu_context_ns_per_key": {"loop": 12, "stream": 8, "default_clef_loop": 21.0,
-                                         "default_clef_stream": 8.7},
-    }
+    kind = WORKLOADS[args.workload][1]
+    run = {"u64": run_u64, "bytes": run_bytes, "serve": run_serve}[kind]
+    rec, ok = run(args, torch, K, P)
     print(json.dumps(rec), flush=True)
-    if not bijective:
+    if not ok:
         sys.exit(3)
 
 

@@ -141,6 +141,111 @@ PTRHASH_API int ptrhash_query(ptrhash_handle *h, const uint64_t *keys, uint64_t 
 PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, const uint64_t *offsets,
                                     uint64_t n_q, void *out, hipStream_t stream);
 
+/* ---- Many MPHFs in one launch (row A8) ---- */
+
+/* One query batch against one loaded MPHF. For a u64-key handle set keys;
+ * for a byte-key handle set data (8-byte aligned, 64 bytes of readable
+ * padding) and offsets (n_q+1 entries). out holds n_q indices of the
+ * handle's index_bits. All pointers are device pointers. */
+typedef struct ptrhash_query_desc {
+    ptrhash_handle *handle;
+    const uint64_t *keys;
+    const uint8_t *data;
+    const uint64_t *offsets;
+    uint64_t n_q;
+    void *out;
+} ptrhash_query_desc;
+
+/*
+ * A reusable launch plan: a device table of up to max_descs batches and a
+ * pinned host staging copy of it. plan_set validates the batches and
+ * writes the staging copy (host only). plan_launch enqueues on stream an
+ * asynchronous copy of the staging table to the device table followed by
+ * one persistent kernel that strides over the tiles of every batch; the
+ * result of each batch equals a separate ptrhash_query/ptrhash_query_bytes
+ * call. plan_launch may be captured into a HIP graph: when the stream is
+ * capturing it copies the whole table, so each replay runs the batches the
+ * latest plan_set wrote. The caller must not call plan_set while an
+ * earlier launch of the same plan may still be copying its staging table
+ * (synchronise the stream, or an event recorded after the launch, first).
+ * Errors: E_INVAL (bad descriptor or count), E_STATE (handle not loaded or
+ * wrong key kind), E_RANGE (k > max_descs), E_NOMEM, E_HIP.
+ */
+typedef struct ptrhash_multi_plan ptrhash_multi_plan;
+PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **out);
+PTRHASH_API int ptrhash_multi_plan_destroy(ptrhash_multi_plan *plan);
+PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_query_desc *descs, int k);
+PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t stream);
+
+/*
+ * Evaluate k batches (descs: host array, copied before return) in one
+ * persistent launch on stream, through an internal ring of plans whose
+ * reuse waits for the launch that last used the slot. Not for use while
+ * the stream is being captured (E_STATE): capture a plan instead.
+ * k == 0 launches nothing. k is limited to ptrhash_multi_max().
+ */
+PTRHASH_API int ptrhash_query_multi(const ptrhash_query_desc *descs, int k, hipStream_t stream);
+PTRHASH_API int ptrhash_multi_max(void);
+
+/* ---- Serving: continuous batching over resident MPHFs (row A8) ---- */
+
+/* streams: launch slots in flight at once (1..16); max_batches: requests per
+ * launch (1..ptrhash_multi_max()); slot_keys: keys one launch can hold (its
+ * device arena; also the largest request); max_queued_keys: admission limit
+ * of keys waiting for a slot (submit returns E_RANGE beyond it). */
+typedef struct ptrhash_server_config {
+    int streams;
+    int max_batches;
+    uint64_t slot_keys;
+    uint64_t max_queued_keys;
+} ptrhash_server_config;
+
+typedef struct ptrhash_server_metrics {
+    uint64_t completed;   /* requests finished since the last reset */
+    uint64_t launches;    /* multi-MPHF launches */
+    uint64_t keys;        /* keys answered */
+    uint64_t queued;      /* requests waiting for a slot now */
+    double p50_us, p99_us, max_us;  /* submit -> indices delivered */
+} ptrhash_server_metrics;
+
+/* One request of a replayed arrival schedule (host keys and output). */
+typedef struct ptrhash_server_request {
+    ptrhash_handle *handle;
+    const uint64_t *keys;
+    uint64_t n_q;
+    void *out;
+    double arrival_us;    /* offset from the start of the replay */
+} ptrhash_server_request;
+
+/*
+ * A server owns `streams` launch slots (device arena, pinned staging, a
+ * multi-MPHF plan and a stream each) and a dispatcher thread. Requests are
+ * host arrays of u64 keys against a loaded u64-key handle; indices are
+ * written to the caller's host buffer (index_bits of that handle). Whenever
+ * a slot is free, queued requests are admitted in arrival order while they
+ * fit its arena and batch count, and run as one launch; slots overlap on the
+ * device, so requests arriving while others run join the next launch. Each
+ * request's result is the same as a lone ptrhash_query of its keys. Keys and
+ * out must stay valid until the request is waited for; every ticket is waited
+ * for at most once. Handles must outlive the requests that use them.
+ * submit: E_RANGE when the request exceeds slot_keys or the queue is full.
+ * wait: blocks until the request is delivered; latency_us may be NULL.
+ * replay: submits reqs at their arrival times (open loop, retrying while the
+ * queue is full), waits for all, and reports the makespan.
+ * destroy drains the queue, then frees everything.
+ */
+typedef struct ptrhash_server ptrhash_server;
+PTRHASH_API int ptrhash_server_default_config(ptrhash_server_config *cfg);
+PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_server **out);
+PTRHASH_API int ptrhash_server_submit(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q,
+                                      void *out, uint64_t *ticket);
+PTRHASH_API int ptrhash_server_wait(ptrhash_server *srv, uint64_t ticket, double *latency_us);
+PTRHASH_API int ptrhash_server_replay(ptrhash_server *srv, const ptrhash_server_request *reqs, uint64_t count,
+                                      double *makespan_s);
+PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics *out);
+PTRHASH_API int ptrhash_server_reset_stats(ptrhash_server *srv);
+PTRHASH_API int ptrhash_server_destroy(ptrhash_server *srv);
+
 /* Kernel choice for a handle's queries: kernel 0 = one key per lane,
  * 1 = keys_per_lane keys per lane with every pilot load issued before the
  * first is used; block = threads per workgroup (64..1024, multiple of 64).
@@ -189,6 +294,11 @@ PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets
 PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const uint8_t *table,
                                      uint64_t table_len, uint64_t *out, int keys_per_lane, int block,
                                      hipStream_t stream);
+/* pure gather: n random byte reads table[hi(mix(i) * table_len)] with no key
+ * or index streams (mix = the SplitMix64 output mixer), spread over `lanes`
+ * threads (a multiple of 256); sink receives one u32 sum per lane. */
+PTRHASH_API int ptrhash_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,
+                                          uint32_t lanes, hipStream_t stream);
 PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane,
                                    int block, hipStream_t stream);
 
@@ -202,6 +312,18 @@ PTRHASH_API int ptrhash_gen_u64_keys(uint64_t seed, uint64_t start, uint64_t cou
                                      hipStream_t stream);
 PTRHASH_API int ptrhash_gen_query_stream(uint64_t n, uint64_t key_seed, uint64_t order_seed, uint64_t start,
                                          uint64_t count, uint64_t *out, hipStream_t stream);
+/* Random strings of a set of n: string s has length 10 + (r mod 41) and
+ * byte j = 0x20 + ((r_j & 0xff) mod 95), r and r_j SplitMix64 outputs of
+ * (seed, s) and (seed ^ 0x2545F4914F6CDD1D, 64 s + j). Entry i of the
+ * generated range is string i (shuffled == 0) or string pi(i) (shuffled,
+ * the Feistel order of gen_query_stream). lengths: count u64 lengths of
+ * entries start..; bytes: writes entry start+i at data + offsets[i], with
+ * offsets (count+1 entries) the caller's running sum of those lengths. */
+PTRHASH_API int ptrhash_gen_string_lengths(uint64_t n, uint64_t seed, uint64_t order_seed, int shuffled,
+                                           uint64_t start, uint64_t count, uint64_t *lengths, hipStream_t stream);
+PTRHASH_API int ptrhash_gen_string_bytes(uint64_t n, uint64_t seed, uint64_t order_seed, int shuffled,
+                                         uint64_t start, uint64_t count, const uint64_t *offsets, uint8_t *data,
+                                         hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 #include "ptrhash.h"
@@ -18,6 +20,14 @@ struct ptrhash_handle {
     uint8_t *d_pilots = nullptr;
     uint8_t *d_remap = nullptr;
     Tuning tuning{};
+};
+
+struct ptrhash_multi_plan {
+    int max = 0;
+    MultiTable *d_table = nullptr;  // device copy read by the kernel
+    MultiTable *h_stage = nullptr;  // pinned host staging copy
+    size_t used_bytes = 0;
+    uint32_t grid = 0;
 };
 
 namespace {
@@ -274,6 +284,160 @@ PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, cons
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query_bytes launch");
 }
 
+// ---- many MPHFs per launch ----
+
+static constexpr int kMultiMax = 4096;
+static constexpr int kRingSlots = 8;
+
+PTRHASH_API int ptrhash_multi_max(void) { return kMultiMax; }
+
+PTRHASH_API int ptrhash_multi_plan_destroy(ptrhash_multi_plan *plan) {
+    if (!plan) return PTRHASH_OK;
+    if (plan->d_table) (void)hipFree(plan->d_table);
+    if (plan->h_stage) (void)hipHostFree(plan->h_stage);
+    delete plan;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **out) {
+    if (!out) return fail(PTRHASH_E_INVAL, "out is NULL");
+    if (max_descs < 1 || max_descs > kMultiMax) return fail(PTRHASH_E_RANGE, "max_descs must be in [1, %d]", kMultiMax);
+    ptrhash_multi_plan *p = new (std::nothrow) ptrhash_multi_plan();
+    if (!p) return fail(PTRHASH_E_NOMEM, "plan allocation failed");
+    p->max = max_descs;
+    const size_t bytes = multi_table_bytes(max_descs);
+    hipError_t e = hipMalloc(&p->d_table, bytes);
+    if (e != hipSuccess) {
+        p->d_table = nullptr;
+        ptrhash_multi_plan_destroy(p);
+        return fail(PTRHASH_E_NOMEM, "hipMalloc for the batch table: %s", hipGetErrorString(e));
+    }
+    e = hipHostMalloc(&p->h_stage, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p->h_stage = nullptr;
+        ptrhash_multi_plan_destroy(p);
+        return fail(PTRHASH_E_NOMEM, "hipHostMalloc for the staging table: %s", hipGetErrorString(e));
+    }
+    std::memset(p->h_stage, 0, bytes);
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+        ptrhash_multi_plan_destroy(p);
+        return hip_fail(e, "device query");
+    }
+    p->grid = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)multi_blocks_per_cu();
+    p->used_bytes = multi_table_bytes(1);
+    *out = p;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_query_desc *descs, int k) {
+    if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
+    if (k < 0 || (k > 0 && !descs)) return fail(PTRHASH_E_INVAL, "bad descriptor array");
+    if (k > plan->max) return fail(PTRHASH_E_RANGE, "%d batches exceed the plan's %d", k, plan->max);
+    // validate everything before touching the staging table
+    for (int i = 0; i < k; ++i) {
+        const ptrhash_query_desc &d = descs[i];
+        if (!d.handle) return fail(PTRHASH_E_INVAL, "batch %d: handle is NULL", i);
+        if (!d.handle->loaded) return fail(PTRHASH_E_STATE, "batch %d: handle has no MPHF loaded", i);
+        if (d.n_q == 0) continue;
+        if (!d.out) return fail(PTRHASH_E_INVAL, "batch %d: out is NULL", i);
+        if (d.handle->params.key_kind == PTRHASH_KEY_U64) {
+            if (!d.keys) return fail(PTRHASH_E_INVAL, "batch %d: keys is NULL for a u64-key MPHF", i);
+        } else {
+            if (!d.data || !d.offsets) return fail(PTRHASH_E_INVAL, "batch %d: data/offsets is NULL", i);
+            if (reinterpret_cast<uintptr_t>(d.data) & 7u)
+                return fail(PTRHASH_E_INVAL, "batch %d: data must be 8-byte aligned", i);
+        }
+    }
+    MultiTable *t = plan->h_stage;
+    uint32_t c = 0;
+    uint64_t tiles = 0;
+    for (int i = 0; i < k; ++i) {
+        const ptrhash_query_desc &d = descs[i];
+        if (d.n_q == 0) continue;
+        MultiDesc &m = t->descs[c++];
+        m.m = device_view(d.handle);
+        m.bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
+        m.out64 = d.handle->params.index_bits == 64;
+        m.keys = m.bytes ? nullptr : d.keys;
+        m.data = m.bytes ? d.data : nullptr;
+        m.offsets = m.bytes ? d.offsets : nullptr;
+        m.out = d.out;
+        m.nq = d.n_q;
+        m.tile_begin = tiles;
+        tiles += (d.n_q + kMultiTile - 1) / kMultiTile;
+    }
+    t->count = c;
+    t->tiles = tiles;
+    plan->used_bytes = multi_table_bytes(c ? (int)c : 1);
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t stream) {
+    if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && plan->h_stage->tiles == 0) return PTRHASH_OK;
+    // a captured copy must cover any later table, so it copies all of it
+    const size_t bytes = capturing ? multi_table_bytes(plan->max) : plan->used_bytes;
+    e = hipMemcpyAsync(plan->d_table, plan->h_stage, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    e = launch_query_multi(plan->d_table, plan->grid, stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query_multi launch");
+}
+
+namespace {
+struct PlanRing {
+    std::mutex mu;
+    ptrhash_multi_plan *plans[kRingSlots] = {};
+    hipEvent_t done[kRingSlots] = {};
+    bool pending[kRingSlots] = {};
+    int next = 0;
+};
+constexpr int kMaxDevices = 64;
+PlanRing g_rings[kMaxDevices];
+}  // namespace
+
+PTRHASH_API int ptrhash_query_multi(const ptrhash_query_desc *descs, int k, hipStream_t stream) {
+    if (k < 0 || (k > 0 && !descs)) return fail(PTRHASH_E_INVAL, "bad descriptor array");
+    if (k > kMultiMax) return fail(PTRHASH_E_RANGE, "%d batches exceed %d", k, kMultiMax);
+    if (k == 0) return PTRHASH_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(PTRHASH_E_STATE, "stream is capturing: capture a plan instead");
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PTRHASH_E_RANGE, "device %d out of range", dev);
+    PlanRing &r = g_rings[dev];
+    std::lock_guard<std::mutex> lock(r.mu);
+    const int slot = r.next;
+    r.next = (r.next + 1) % kRingSlots;
+    if (!r.plans[slot]) {
+        int rc = ptrhash_multi_plan_create(kMultiMax, &r.plans[slot]);
+        if (rc) return rc;
+        if ((e = hipEventCreateWithFlags(&r.done[slot], hipEventDisableTiming)) != hipSuccess) {
+            ptrhash_multi_plan_destroy(r.plans[slot]);
+            r.plans[slot] = nullptr;
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    if (r.pending[slot]) {
+        if ((e = hipEventSynchronize(r.done[slot])) != hipSuccess) return hip_fail(e, "waiting for a plan slot");
+        r.pending[slot] = false;
+    }
+    int rc = ptrhash_multi_plan_set(r.plans[slot], descs, k);
+    if (rc) return rc;
+    rc = ptrhash_multi_plan_launch(r.plans[slot], stream);
+    if (rc) return rc;
+    if ((e = hipEventRecord(r.done[slot], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    r.pending[slot] = true;
+    return PTRHASH_OK;
+}
+
 PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const uint8_t *table, uint64_t table_len,
                                      uint64_t *out, int keys_per_lane, int block, hipStream_t stream) {
     if (!valid_tuning(kKernelPipelined, keys_per_lane, block)) return fail(PTRHASH_E_INVAL, "bad tuning");
@@ -284,6 +448,15 @@ PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const u
     if (rc) return rc;
     const hipError_t e = launch_bench_gather(keys, n_q, table, table_len, out, keys_per_lane, block, stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "gather launch");
+}
+
+PTRHASH_API int ptrhash_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,
+                                          uint32_t lanes, hipStream_t stream) {
+    if (n == 0) return PTRHASH_OK;
+    if (!table || !sink || table_len == 0) return fail(PTRHASH_E_INVAL, "NULL or empty argument");
+    if (lanes < 256 || lanes % 256) return fail(PTRHASH_E_INVAL, "lanes must be a positive multiple of 256");
+    const hipError_t e = launch_bench_gather_pure(n, table, table_len, sink, lanes / 256, stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "pure gather launch");
 }
 
 PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane, int block,

@@ -18,6 +18,36 @@ struct Tuning {
 
 bool valid_tuning(int kernel, int keys_per_lane, int block);
 
+// Persistent multi-batch launch: tile = kMultiK keys per lane x kMultiBlock lanes.
+constexpr int kMultiK = 4;
+constexpr int kMultiBlock = 256;
+constexpr uint64_t kMultiTile = (uint64_t)kMultiK * kMultiBlock;
+
+struct MultiDesc {
+    DevMphf m;
+    const uint64_t *keys;     // u64 keys (bytes == 0)
+    const uint8_t *data;      // byte keys (bytes == 1)
+    const uint64_t *offsets;
+    void *out;
+    uint64_t nq;
+    uint64_t tile_begin;      // first global tile of this batch
+    uint32_t bytes, out64;
+};
+
+struct MultiTable {
+    uint32_t count;           // batches (>= 1)
+    uint32_t pad_;
+    uint64_t tiles;           // total tiles
+    MultiDesc descs[1];       // count entries follow
+};
+
+inline size_t multi_table_bytes(int max_descs) {
+    return sizeof(MultiTable) + sizeof(MultiDesc) * (size_t)(max_descs > 1 ? max_descs - 1 : 0);
+}
+
+hipError_t launch_query_multi(const MultiTable *table, uint32_t grid, hipStream_t s);
+int multi_blocks_per_cu();  // resident blocks of query_multi per compute unit
+
 hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
                             const Tuning &t, hipStream_t s);
 hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
@@ -25,6 +55,8 @@ hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint6
 
 hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t table_len,
                                uint64_t *out, int keys_per_lane, int block, hipStream_t s);
+hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T, uint32_t *sink, uint32_t grid,
+                                    hipStream_t s);
 hipError_t launch_bench_copy(const uint64_t *keys, uint64_t nq, uint64_t *out, int keys_per_lane, int block,
                              hipStream_t s);
 

@@ -15,6 +15,8 @@
 //    round trip. Keys and indices are streamed with non-temporal loads and
 //    stores so that they do not evict pilots from the L2 and MALL.
 //  - query_bytes<K>: the same for packed byte-string keys.
+//  - query_multi: a persistent launch over many batches, each against its
+//    own resident MPHF, described by a table in device memory.
 #include "internal.h"
 #include "mphf_device.h"
 
@@ -69,18 +71,28 @@ __device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], con
         if (need[j]) v[j] = clef_value(r[j], idx[j]);
 }
 
-template <int K, typename OutT>
-__global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restrict__ keys, uint64_t nq,
-                                                        OutT *__restrict__ out, DevMphf m) {
-    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    const uint32_t stride = blockDim.x;
+// One tile of K*stride keys starting at base: lane tid handles keys
+// base + tid + j*stride, j < K. Bytes selects packed byte-string keys.
+template <int K, typename OutT, bool Bytes>
+__device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *__restrict__ keys,
+                                             const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets,
+                                             uint64_t nq, OutT *__restrict__ out, uint64_t base, uint32_t stride) {
     uint64_t h[K];
     bool ok[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * stride;
         ok[j] = i < nq;
-        h[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
+        if (Bytes) {
+            if (ok[j]) {
+                const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+                h[j] = hash_bytes(m.seed, data, o0, o1 - o0);
+            } else {
+                h[j] = 0;
+            }
+        } else {
+            h[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
+        }
     }
     uint32_t part[K], pil[K];
 #pragma unroll
@@ -100,38 +112,54 @@ __global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restri
 }
 
 template <int K, typename OutT>
+__global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restrict__ keys, uint64_t nq,
+                                                        OutT *__restrict__ out, DevMphf m) {
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
+    process_tile<K, OutT, false>(m, keys, nullptr, nullptr, nq, out, base, blockDim.x);
+}
+
+template <int K, typename OutT>
 __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict__ data,
                                                       const uint64_t *__restrict__ offsets, uint64_t nq,
                                                       OutT *__restrict__ out, DevMphf m) {
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    const uint32_t stride = blockDim.x;
-    uint64_t h[K];
-    bool ok[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint64_t i = base + (uint64_t)j * stride;
-        ok[j] = i < nq;
-        if (ok[j]) {
-            const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
-            h[j] = hash_bytes(m.seed, data, o0, o1 - o0);
-        } else {
-            h[j] = 0;
+    process_tile<K, OutT, true>(m, nullptr, data, offsets, nq, out, base, blockDim.x);
+}
+
+// Persistent launch over a table of query batches (each against its own
+// resident MPHF). Every batch is cut into tiles of kMultiK*blockDim keys;
+// tiles are numbered globally (MultiDesc::tile_begin is a prefix sum) and
+// the grid strides over them, so batches of any mix of sizes share one
+// launch. The header (batch count, tile count) lives in device memory next
+// to the batches, so a captured launch can be replayed over new batches.
+__global__ void __launch_bounds__(kMultiBlock) query_multi(const MultiTable *__restrict__ table) {
+    const uint32_t count = table->count;
+    const uint64_t tiles = table->tiles;
+    const MultiDesc *__restrict__ d = table->descs;
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        // last descriptor whose first tile is <= t (uniform across the block)
+        uint32_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (d[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
-    }
-    uint32_t part[K], pil[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint64_t b = bucket_of(m, h[j], part[j]);
-        pil[j] = ok[j] ? m.pilots[b] : 0;
-    }
-    uint64_t v[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) v[j] = slot_of(m, h[j], part[j], pil[j]);
-    finish_k<K>(m, v, ok);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint64_t i = base + (uint64_t)j * stride;
-        if (ok[j]) nt_store((OutT)v[j], out + i);
+        const MultiDesc &q = d[lo];
+        const uint64_t base = (t - q.tile_begin) * (uint64_t)(kMultiK * kMultiBlock) + threadIdx.x;
+        if (q.bytes) {
+            if (q.out64)
+                process_tile<kMultiK, uint64_t, true>(q.m, nullptr, q.data, q.offsets, q.nq,
+                                                      static_cast<uint64_t *>(q.out), base, kMultiBlock);
+            else
+                process_tile<kMultiK, uint32_t, true>(q.m, nullptr, q.data, q.offsets, q.nq,
+                                                      static_cast<uint32_t *>(q.out), base, kMultiBlock);
+        } else {
+            if (q.out64)
+                process_tile<kMultiK, uint64_t, false>(q.m, q.keys, nullptr, nullptr, q.nq,
+                                                       static_cast<uint64_t *>(q.out), base, kMultiBlock);
+            else
+                process_tile<kMultiK, uint32_t, false>(q.m, q.keys, nullptr, nullptr, q.nq,
+                                                       static_cast<uint32_t *>(q.out), base, kMultiBlock);
+        }
     }
 }
 
@@ -200,6 +228,18 @@ hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint6
                               void *out, bool out64, const Tuning &t, hipStream_t s) {
     return out64 ? launch_bytes_t<uint64_t>(m, data, offsets, nq, out, t, s)
                  : launch_bytes_t<uint32_t>(m, data, offsets, nq, out, t, s);
+}
+
+int multi_blocks_per_cu() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, query_multi, kMultiBlock, 0) != hipSuccess || blocks < 1)
+        blocks = 4;
+    return blocks;
+}
+
+hipError_t launch_query_multi(const MultiTable *table, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(query_multi, dim3(grid), dim3(kMultiBlock), 0, s, table);
+    return hipGetLastError();
 }
 
 }  // namespace ptrhash

@@ -47,7 +47,42 @@ __global__ void __launch_bounds__(1024) bench_copy_k(const uint64_t *__restrict_
     }
 }
 
+// Random byte gathers with no streams: index i is hi(mix(i) * T) (SplitMix64
+// output mixer), four gathers in flight per lane per step, one u32 sum per
+// lane written at the end so the loads stay live.
+__device__ inline uint64_t sm_mix(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return z;
+}
+
+__global__ void __launch_bounds__(256) bench_gather_pure_k(uint64_t n, const uint8_t *__restrict__ table, uint64_t T,
+                                                           uint32_t *__restrict__ sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (uint64_t i = t; i < n; i += 4 * stride) {
+        uint32_t b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t k = i + j * stride;
+            b[j] = k < n ? table[__umul64hi(sm_mix(k), T)] : 0;
+        }
+        acc += b[0] + b[1] + b[2] + b[3];
+    }
+    sink[t] = acc;
+}
+
 static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T, uint32_t *sink, uint32_t grid,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL(bench_gather_pure_k, dim3(grid), dim3(256), 0, s, n, table, T, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t T, uint64_t *out,
                                int K, int block, hipStream_t s) {

@@ -1,0 +1,374 @@
+// Serving core: continuous batching of query requests against resident
+// MPHFs (the throughput argument of Appendix A -- many queries known in
+// advance -- recovered from a stream of independent small requests).
+//
+// Requests (host keys in, host indices out) queue up; a dispatcher thread
+// owns `streams` launch slots, each with a device arena of `slot_keys` keys
+// and a multi-batch plan. Whenever a slot is free it admits queued requests
+// in arrival order while they fit the arena (memory) and the plan (batch
+// count), copies their keys to the device, runs one persistent multi-MPHF
+// launch and copies the indices back, all asynchronously on the slot's
+// stream; slots overlap on the device. Completed slots are retired by
+// polling their events, and each request's latency (submit -> indices in
+// the caller's buffer) is recorded.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "errors.h"
+#include "internal.h"
+#include "ptrhash.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    ptrhash_handle *handle = nullptr;
+    const uint64_t *keys = nullptr;
+    uint64_t n_q = 0;
+    void *out = nullptr;
+    uint32_t out_bytes = 4;   // bytes per index
+    Clock::time_point t_submit{};
+    uint64_t key_off = 0;     // placement inside the slot arena
+    uint64_t out_off = 0;     // byte offset inside the slot's output arena
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    ptrhash_multi_plan *plan = nullptr;
+    uint64_t *d_keys = nullptr, *h_keys = nullptr;
+    uint8_t *d_out = nullptr, *h_out = nullptr;
+    std::vector<Request> reqs;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct ptrhash_server {
+    ptrhash_server_config cfg{};
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    uint64_t queued_keys = 0;
+    uint64_t next_ticket = 1;
+    std::unordered_set<uint64_t> outstanding;       // submitted, not finished
+    std::unordered_map<uint64_t, double> finished;  // ticket -> latency (us), until waited for
+    std::vector<double> latencies;                   // all completed requests
+    uint64_t launches = 0, completed = 0, keys_done = 0;
+    int error = PTRHASH_OK;
+    bool stop = false;
+    int device = 0;
+    std::thread worker;
+};
+
+namespace {
+
+int hip_err(hipError_t e, const char *what) {
+    return ptrhash::set_error(PTRHASH_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_slot(Slot &s) {
+    if (s.plan) ptrhash_multi_plan_destroy(s.plan);
+    if (s.d_keys) (void)hipFree(s.d_keys);
+    if (s.d_out) (void)hipFree(s.d_out);
+    if (s.h_keys) (void)hipHostFree(s.h_keys);
+    if (s.h_out) (void)hipHostFree(s.h_out);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    s = Slot{};
+}
+
+// Retire a finished slot: copy indices to the callers' buffers.
+void retire(ptrhash_server *srv, Slot &s) {
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> lock(srv->mu);
+    for (const Request &r : s.reqs) {
+        std::memcpy(r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
+        const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
+        srv->outstanding.erase(r.ticket);
+        srv->finished[r.ticket] = us;
+        srv->latencies.push_back(us);
+        srv->completed++;
+        srv->keys_done += r.n_q;
+    }
+    s.reqs.clear();
+    s.busy = false;
+    srv->cv_done.notify_all();
+}
+
+// Admit queued requests into a free slot and launch them. Called with the
+// lock held; releases it around the copies and the launch.
+int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
+    uint64_t used = 0, out_used = 0;
+    while (!srv->queue.empty() && (int)s.reqs.size() < srv->cfg.max_batches) {
+        Request &r = srv->queue.front();
+        if (used + r.n_q > srv->cfg.slot_keys) break;
+        r.key_off = used;
+        r.out_off = out_used;
+        used += r.n_q;
+        out_used += (r.n_q * r.out_bytes + 7) & ~7ull;
+        srv->queued_keys -= r.n_q;
+        s.reqs.push_back(r);
+        srv->queue.pop_front();
+    }
+    if (s.reqs.empty()) return PTRHASH_OK;
+    s.busy = true;
+    lock.unlock();
+    std::vector<ptrhash_query_desc> descs(s.reqs.size());
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+        const Request &r = s.reqs[i];
+        std::memcpy(s.h_keys + r.key_off, r.keys, r.n_q * sizeof(uint64_t));
+        descs[i] = ptrhash_query_desc{r.handle, s.d_keys + r.key_off, nullptr, nullptr, r.n_q, s.d_out + r.out_off};
+    }
+    int rc = ptrhash_multi_plan_set(s.plan, descs.data(), (int)descs.size());
+    hipError_t e = hipSuccess;
+    if (rc == PTRHASH_OK) {
+        e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess) rc = ptrhash_multi_plan_launch(s.plan, s.stream);
+        if (e == hipSuccess && rc == PTRHASH_OK)
+            e = hipMemcpyAsync(s.h_out, s.d_out, out_used, hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess && rc == PTRHASH_OK) e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) rc = hip_err(e, "serving launch");
+    }
+    lock.lock();
+    if (rc == PTRHASH_OK) srv->launches++;
+    return rc;
+}
+
+void run(ptrhash_server *srv) {
+    (void)hipSetDevice(srv->device);
+    std::unique_lock<std::mutex> lock(srv->mu);
+    for (;;) {
+        bool any_busy = false;
+        // retire finished slots
+        for (Slot &s : srv->slots) {
+            if (!s.busy) continue;
+            lock.unlock();
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipSuccess) {
+                retire(srv, s);
+            } else if (q != hipErrorNotReady) {
+                lock.lock();
+                srv->error = hip_err(q, "serving completion");
+                srv->stop = true;
+                srv->cv_done.notify_all();
+                return;
+            }
+            lock.lock();
+            any_busy |= s.busy;
+        }
+        // admit into free slots
+        for (Slot &s : srv->slots) {
+            if (s.busy || srv->queue.empty()) continue;
+            const int rc = admit(srv, s, lock);
+            if (rc != PTRHASH_OK) {
+                srv->error = rc;
+                srv->stop = true;
+                srv->cv_done.notify_all();
+                return;
+            }
+            any_busy |= s.busy;
+        }
+        if (srv->stop && srv->queue.empty() && !any_busy) return;
+        if (any_busy)
+            srv->cv_work.wait_for(lock, std::chrono::microseconds(5));
+        else
+            srv->cv_work.wait(lock, [&] { return srv->stop || !srv->queue.empty(); });
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+PTRHASH_API int ptrhash_server_default_config(ptrhash_server_config *cfg) {
+    if (!cfg) return ptrhash::set_error(PTRHASH_E_INVAL, "cfg is NULL");
+    cfg->streams = 2;
+    cfg->max_batches = 1024;
+    cfg->slot_keys = 1u << 22;
+    cfg->max_queued_keys = 1ull << 28;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_server **out) {
+    if (!cfg || !out) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL argument");
+    if (cfg->streams < 1 || cfg->streams > 16) return ptrhash::set_error(PTRHASH_E_INVAL, "streams must be 1..16");
+    if (cfg->max_batches < 1 || cfg->max_batches > ptrhash_multi_max())
+        return ptrhash::set_error(PTRHASH_E_INVAL, "max_batches must be 1..%d", ptrhash_multi_max());
+    if (cfg->slot_keys < 1 || cfg->slot_keys > (1ull << 32))
+        return ptrhash::set_error(PTRHASH_E_INVAL, "slot_keys must be 1..2^32");
+    if (cfg->max_queued_keys < cfg->slot_keys)
+        return ptrhash::set_error(PTRHASH_E_INVAL, "max_queued_keys must be >= slot_keys");
+    ptrhash_server *srv = new (std::nothrow) ptrhash_server();
+    if (!srv) return ptrhash::set_error(PTRHASH_E_NOMEM, "server allocation failed");
+    srv->cfg = *cfg;
+    hipError_t e = hipGetDevice(&srv->device);
+    int rc = e == hipSuccess ? PTRHASH_OK : hip_err(e, "hipGetDevice");
+    srv->slots.resize(cfg->streams);
+    for (Slot &s : srv->slots) {
+        if (rc) break;
+        const uint64_t kb = cfg->slot_keys * sizeof(uint64_t);
+        const uint64_t ob = cfg->slot_keys * sizeof(uint64_t) + 8 * (uint64_t)cfg->max_batches;
+        if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
+            rc = hip_err(e, "stream/event creation");
+            break;
+        }
+        if (hipMalloc(&s.d_keys, kb) != hipSuccess || hipMalloc(&s.d_out, ob) != hipSuccess ||
+            hipHostMalloc(&s.h_keys, kb, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&s.h_out, ob, hipHostMallocDefault) != hipSuccess) {
+            rc = ptrhash::set_error(PTRHASH_E_NOMEM, "serving arena allocation failed");
+            break;
+        }
+        rc = ptrhash_multi_plan_create(cfg->max_batches, &s.plan);
+    }
+    if (rc) {
+        for (Slot &s : srv->slots) free_slot(s);
+        delete srv;
+        return rc;
+    }
+    srv->worker = std::thread(run, srv);
+    *out = srv;
+    return PTRHASH_OK;
+}
+
+static int submit_at(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, void *out,
+                     uint64_t *ticket, Clock::time_point arrival) {
+    if (!srv || !h || !ticket || (n_q && (!keys || !out))) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL argument");
+    ptrhash_params p;
+    int rc = ptrhash_get_params(h, &p);
+    if (rc) return rc;
+    if (p.key_kind != PTRHASH_KEY_U64) return ptrhash::set_error(PTRHASH_E_STATE, "serving takes u64-key MPHFs");
+    if (n_q > srv->cfg.slot_keys)
+        return ptrhash::set_error(PTRHASH_E_RANGE, "request of %llu keys exceeds slot_keys",
+                                  (unsigned long long)n_q);
+    Request r;
+    r.handle = h;
+    r.keys = keys;
+    r.n_q = n_q;
+    r.out = out;
+    r.out_bytes = p.index_bits / 8;
+    std::unique_lock<std::mutex> lock(srv->mu);
+    if (srv->error) return ptrhash::set_error(srv->error, "server stopped after an error");
+    if (srv->stop) return ptrhash::set_error(PTRHASH_E_STATE, "server is stopping");
+    if (srv->queued_keys + n_q > srv->cfg.max_queued_keys)
+        return ptrhash::set_error(PTRHASH_E_RANGE, "queue full");
+    r.ticket = srv->next_ticket++;
+    r.t_submit = arrival;
+    *ticket = r.ticket;
+    if (n_q == 0) {
+        srv->finished[r.ticket] = 0.0;
+        srv->completed++;
+        srv->latencies.push_back(0.0);
+        srv->cv_done.notify_all();
+        return PTRHASH_OK;
+    }
+    srv->queued_keys += n_q;
+    srv->outstanding.insert(r.ticket);
+    srv->queue.push_back(r);
+    srv->cv_work.notify_one();
+    return PTRHASH_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+PTRHASH_API int ptrhash_server_submit(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q,
+                                      void *out, uint64_t *ticket) {
+    return submit_at(srv, h, keys, n_q, out, ticket, Clock::now());
+}
+
+PTRHASH_API int ptrhash_server_wait(ptrhash_server *srv, uint64_t ticket, double *latency_us) {
+    if (!srv) return ptrhash::set_error(PTRHASH_E_INVAL, "server is NULL");
+    std::unique_lock<std::mutex> lock(srv->mu);
+    if (!srv->outstanding.count(ticket) && !srv->finished.count(ticket))
+        return ptrhash::set_error(PTRHASH_E_INVAL, "unknown or already collected ticket");
+    srv->cv_done.wait(lock, [&] { return srv->finished.count(ticket) || srv->error; });
+    auto it = srv->finished.find(ticket);
+    if (it == srv->finished.end()) return ptrhash::set_error(srv->error, "server stopped after an error");
+    if (latency_us) *latency_us = it->second;
+    srv->finished.erase(it);
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics *st) {
+    if (!srv || !st) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    st->completed = srv->completed;
+    st->launches = srv->launches;
+    st->keys = srv->keys_done;
+    st->queued = srv->queue.size();
+    std::vector<double> v(srv->latencies);
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double q) { return v.empty() ? 0.0 : v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
+    st->p50_us = pct(0.50);
+    st->p99_us = pct(0.99);
+    st->max_us = v.empty() ? 0.0 : v.back();
+    return srv->error;
+}
+
+PTRHASH_API int ptrhash_server_reset_stats(ptrhash_server *srv) {
+    if (!srv) return ptrhash::set_error(PTRHASH_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->latencies.clear();
+    srv->completed = srv->launches = srv->keys_done = 0;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_server_replay(ptrhash_server *srv, const ptrhash_server_request *reqs, uint64_t count,
+                                      double *makespan_s) {
+    if (!srv || (count && !reqs)) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL argument");
+    std::vector<uint64_t> tickets(count);
+    const auto t0 = Clock::now();
+    for (uint64_t i = 0; i < count; ++i) {
+        const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
+                                  std::chrono::duration<double, std::micro>(reqs[i].arrival_us));
+        while (Clock::now() < due) {
+        }
+        for (;;) {
+            const int rc = submit_at(srv, reqs[i].handle, reqs[i].keys, reqs[i].n_q, reqs[i].out, &tickets[i], due);
+            if (rc == PTRHASH_OK) break;
+            if (rc != PTRHASH_E_RANGE || reqs[i].n_q > srv->cfg.slot_keys) return rc;
+            std::this_thread::yield();  // queue full: the open loop backs off
+        }
+    }
+    for (uint64_t i = 0; i < count; ++i) {
+        const int rc = ptrhash_server_wait(srv, tickets[i], nullptr);
+        if (rc) return rc;
+    }
+    if (makespan_s) *makespan_s = std::chrono::duration<double>(Clock::now() - t0).count();
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_server_destroy(ptrhash_server *srv) {
+    if (!srv) return PTRHASH_OK;
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        srv->stop = true;
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    for (Slot &s : srv->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        free_slot(s);
+    }
+    const int err = srv->error;
+    delete srv;
+    return err;
+}
+
+}  // extern "C"

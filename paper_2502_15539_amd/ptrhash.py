@@ -50,6 +50,35 @@ class Params(C.Structure):
         return Params.from_buffer_copy(self)
 
 
+class QueryDesc(C.Structure):
+    _fields_ = [
+        ("handle", C.c_void_p),
+        ("keys", C.c_void_p),
+        ("data", C.c_void_p),
+        ("offsets", C.c_void_p),
+        ("n_q", C.c_uint64),
+        ("out", C.c_void_p),
+    ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("streams", C.c_int), ("max_batches", C.c_int), ("slot_keys", C.c_uint64),
+                ("max_queued_keys", C.c_uint64)]
+
+
+class ServerMetrics(C.Structure):
+    _fields_ = [("completed", C.c_uint64), ("launches", C.c_uint64), ("keys", C.c_uint64), ("queued", C.c_uint64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerRequest(C.Structure):
+    _fields_ = [("handle", C.c_void_p), ("keys", C.c_void_p), ("n_q", C.c_uint64), ("out", C.c_void_p),
+                ("arrival_us", C.c_double)]
+
+
 class BuildInfo(C.Structure):
     _fields_ = [
         ("attempts", C.c_uint64),
@@ -77,7 +106,28 @@ _SIGS = {
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
                                        C.c_void_p]),
+    "ptrhash_bench_gather_pure": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
+                                            C.c_void_p]),
     "ptrhash_bench_copy": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "ptrhash_multi_plan_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+    "ptrhash_multi_plan_destroy": (C.c_int, [C.c_void_p]),
+    "ptrhash_multi_plan_set": (C.c_int, [C.c_void_p, C.POINTER(QueryDesc), C.c_int]),
+    "ptrhash_multi_plan_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ptrhash_query_multi": (C.c_int, [C.POINTER(QueryDesc), C.c_int, C.c_void_p]),
+    "ptrhash_multi_max": (C.c_int, []),
+    "ptrhash_server_default_config": (C.c_int, [C.POINTER(ServerConfig)]),
+    "ptrhash_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    "ptrhash_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                        C.POINTER(C.c_uint64)]),
+    "ptrhash_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "ptrhash_server_replay": (C.c_int, [C.c_void_p, C.POINTER(ServerRequest), C.c_uint64, C.POINTER(C.c_double)]),
+    "ptrhash_server_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerMetrics)]),
+    "ptrhash_server_reset_stats": (C.c_int, [C.c_void_p]),
+    "ptrhash_server_destroy": (C.c_int, [C.c_void_p]),
+    "ptrhash_gen_string_lengths": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, C.c_uint64, C.c_uint64,
+                                             C.c_void_p, C.c_void_p]),
+    "ptrhash_gen_string_bytes": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, C.c_uint64, C.c_uint64,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptrhash_gen_u64_keys": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p]),
     "ptrhash_gen_query_stream": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p,
                                            C.c_void_p]),
@@ -246,6 +296,12 @@ def bench_gather(keys, table, out, keys_per_lane=4, block=256, stream=None):
                                       int(keys_per_lane), int(block), _stream(stream)), "ptrhash_bench_gather")
 
 
+def bench_gather_pure(n, table, sink, stream=None):
+    """sink: int32 cuda tensor, its length (a multiple of 256) = lanes."""
+    _check(lib().ptrhash_bench_gather_pure(int(n), _dev_ptr(table), table.numel(), _dev_ptr(sink), sink.numel(),
+                                           _stream(stream)), "ptrhash_bench_gather_pure")
+
+
 def bench_copy(keys, out, keys_per_lane=4, block=256, stream=None):
     _check(lib().ptrhash_bench_copy(_dev_ptr(keys), keys.numel(), _dev_ptr(out), int(keys_per_lane), int(block),
                                     _stream(stream)), "ptrhash_bench_copy")
@@ -263,3 +319,145 @@ def gen_query_stream(out, n, key_seed, order_seed, start=0, stream=None):
     _check(lib().ptrhash_gen_query_stream(int(n), int(key_seed), int(order_seed), int(start), out.numel(),
                                           _dev_ptr(out), _stream(stream)), "ptrhash_gen_query_stream")
     return out
+
+
+def make_descs(batches):
+    """batches: list of (Mphf, keys_or_(data, offsets), out) with cuda tensors."""
+    arr = (QueryDesc * max(1, len(batches)))()
+    for i, (m, keys, out) in enumerate(batches):
+        d = arr[i]
+        d.handle = m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle
+        if isinstance(keys, tuple):
+            data, offsets = keys
+            d.data, d.offsets, d.n_q = data.data_ptr(), offsets.data_ptr(), offsets.numel() - 1
+        else:
+            d.keys, d.n_q = keys.data_ptr(), keys.numel()
+        d.out = out.data_ptr() if out is not None else None
+    return arr
+
+
+def query_multi(batches, stream=None):
+    """One persistent launch over all batches (see ptrhash_query_multi)."""
+    arr = make_descs(batches)
+    _check(lib().ptrhash_query_multi(arr, len(batches), _stream(stream)), "ptrhash_query_multi")
+
+
+class MultiPlan:
+    """A reusable, graph-capturable multi-batch launch (ptrhash_multi_plan_*)."""
+
+    def __init__(self, max_descs: int = 64):
+        h = C.c_void_p()
+        _check(lib().ptrhash_multi_plan_create(int(max_descs), C.byref(h)), "ptrhash_multi_plan_create")
+        self._h = h
+
+    def set(self, batches):
+        arr = make_descs(batches)
+        _check(lib().ptrhash_multi_plan_set(self._h, arr, len(batches)), "ptrhash_multi_plan_set")
+
+    def launch(self, stream=None):
+        _check(lib().ptrhash_multi_plan_launch(self._h, _stream(stream)), "ptrhash_multi_plan_launch")
+
+    def close(self):
+        if self._h:
+            lib().ptrhash_multi_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching query server over resident MPHFs (host keys in,
+    host indices out); see ptrhash_server_* in include/ptrhash.h."""
+
+    def __init__(self, streams=None, max_batches=None, slot_keys=None, max_queued_keys=None):
+        cfg = ServerConfig()
+        _check(lib().ptrhash_server_default_config(C.byref(cfg)), "ptrhash_server_default_config")
+        if streams is not None:
+            cfg.streams = streams
+        if max_batches is not None:
+            cfg.max_batches = max_batches
+        if slot_keys is not None:
+            cfg.slot_keys = slot_keys
+        if max_queued_keys is not None:
+            cfg.max_queued_keys = max_queued_keys
+        elif cfg.max_queued_keys < cfg.slot_keys:
+            cfg.max_queued_keys = cfg.slot_keys
+        self.cfg = cfg
+        h = C.c_void_p()
+        _check(lib().ptrhash_server_create(C.byref(cfg), C.byref(h)), "ptrhash_server_create")
+        self._h = h
+
+    def submit(self, mphf: "Mphf", keys: np.ndarray, out: np.ndarray) -> int:
+        """keys: host uint64 array; out: host uint32/uint64 array (the handle's
+        index width). Both must stay alive until wait() returns."""
+        assert keys.dtype == np.uint64 and keys.flags.c_contiguous and out.flags.c_contiguous
+        want = np.uint64 if mphf.params.index_bits == 64 else np.uint32
+        if out.dtype != want or len(out) < len(keys):
+            raise ValueError(f"out must be {np.dtype(want).name}[{len(keys)}]")
+        t = C.c_uint64()
+        _check(lib().ptrhash_server_submit(self._h, mphf.handle, _np_ptr(keys), len(keys), _np_ptr(out),
+                                           C.byref(t)), "ptrhash_server_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        lat = C.c_double()
+        _check(lib().ptrhash_server_wait(self._h, int(ticket), C.byref(lat)), "ptrhash_server_wait")
+        return lat.value
+
+    def replay(self, reqs) -> float:
+        """reqs: list of (Mphf, keys ndarray, out ndarray, arrival_us)."""
+        arr = (ServerRequest * max(1, len(reqs)))()
+        for i, (m, k, o, t) in enumerate(reqs):
+            arr[i].handle = m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle
+            arr[i].keys = k.ctypes.data if k.size else None
+            arr[i].n_q = len(k)
+            arr[i].out = o.ctypes.data if o.size else None
+            arr[i].arrival_us = float(t)
+        span = C.c_double()
+        _check(lib().ptrhash_server_replay(self._h, arr, len(reqs), C.byref(span)), "ptrhash_server_replay")
+        return span.value
+
+    def stats(self) -> dict:
+        m = ServerMetrics()
+        _check(lib().ptrhash_server_stats(self._h, C.byref(m)), "ptrhash_server_stats")
+        return m.as_dict()
+
+    def reset_stats(self):
+        _check(lib().ptrhash_server_reset_stats(self._h), "ptrhash_server_reset_stats")
+
+    def close(self):
+        if self._h:
+            rc = lib().ptrhash_server_destroy(self._h)
+            self._h = None
+            _check(rc, "ptrhash_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gen_strings(n, seed, order_seed=0, shuffled=False, start=0, count=None, device="cuda", pad=64):
+    """Device copy of strings start.. of the n-string set (or of its shuffled
+    order): returns (data uint8 tensor with `pad` zero bytes after the last
+    string, offsets int64 tensor of count+1 entries starting at 0)."""
+    import torch
+
+    count = n - start if count is None else count
+    lens = torch.empty(count, dtype=torch.int64, device=device)
+    _check(lib().ptrhash_gen_string_lengths(int(n), int(seed), int(order_seed), int(bool(shuffled)), int(start),
+                                            count, _dev_ptr(lens), _stream(None)), "ptrhash_gen_string_lengths")
+    offsets = torch.zeros(count + 1, dtype=torch.int64, device=device)
+    torch.cumsum(lens, 0, out=offsets[1:])
+    del lens
+    total = int(offsets[-1])
+    data = torch.zeros(total + pad, dtype=torch.uint8, device=device)
+    _check(lib().ptrhash_gen_string_bytes(int(n), int(seed), int(order_seed), int(bool(shuffled)), int(start),
+                                          count, _dev_ptr(offsets), _dev_ptr(data), _stream(None)),
+           "ptrhash_gen_string_bytes")
+    return data, offsets

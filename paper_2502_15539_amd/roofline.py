@@ -1,0 +1,59 @@
+"""Random-gather roofline of the device, as a function of table size.
+
+    python -m paper_2502_15539_amd.roofline [--n 1e9]
+
+For each table size T (from L2-resident to far beyond the MALL) it times,
+on n keys: the streaming gather (u64 key in, one random byte of T, u64 out;
+the memory pattern of a query), the pure gather (random bytes only, no
+streams) and, once, the stream copy (16 B per key). Prints one JSON object.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+from . import ptrhash as P
+
+SIZES = [1 << 20, 4 << 20, 16 << 20, 64 << 20, 128 << 20, 256 << 20, 285_920_472, 512 << 20, 1 << 30, 4 << 30,
+         16 << 30]
+
+
+def main():
+    import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=float, default=1e9)
+    ap.add_argument("--reps", type=int, default=4)
+    args = ap.parse_args()
+    n = int(args.n)
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    P.gen_u64_keys(keys, 1)
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    sink = torch.empty(256 * 8192, dtype=torch.int32, device="cuda")
+
+    def t(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.reps
+
+    res = {"n": n, "copy_ms": min(t(lambda: P.bench_copy(keys, out, k, 256)) for k in (1, 2, 4)), "tables": []}
+    for T in SIZES:
+        table = torch.randint(0, 256, (T,), dtype=torch.uint8, device="cuda")
+        g = min(t(lambda: P.bench_gather(keys, table, out, k, b)) for k in (1, 4) for b in (256, 512))
+        pure = t(lambda: P.bench_gather_pure(n, table, sink))
+        res["tables"].append({"table_bytes": T, "gather_ms": g, "gather_G_per_s": n / g / 1e6,
+                              "pure_gather_ms": pure, "pure_G_per_s": n / pure / 1e6})
+        print(f"T={T / 2**20:8.1f} MiB  gather {g:7.3f} ms ({n / g / 1e6:6.1f} G/s)  "
+              f"pure {pure:7.3f} ms ({n / pure / 1e6:6.1f} G/s)", flush=True)
+        del table
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

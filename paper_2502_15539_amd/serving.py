@@ -1,0 +1,109 @@
+"""Serving workload driver: many resident MPHFs, Poisson arrivals of query
+batches of mixed sizes, continuous batching through ``ptrhash.Server``.
+
+Workload: 64 MPHFs with n log-uniform in [1e4, 1e7] over uniform u64 keys
+(Default parameters, u32 indices); requests target a uniformly chosen MPHF
+with a batch of member keys (drawn with replacement) of size log-uniform in
+[1, 65536]. The saturated request rate is measured first (every request
+queued at t = 0), then open-loop Poisson arrivals at fractions of it; each
+run reports p50/p99 latency (arrival -> indices delivered) and throughput.
+The comparison is one plain one-key-per-lane launch per request on the same
+GPU (keys copied in, one query, indices copied out, in arrival order).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import keygen as K
+from . import ptrhash as P
+
+
+def build_fleet(count=64, lo=10**4, hi=10**7, seed=5, threads=0, log=print):
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(np.log(lo) + rng.uniform(0, 1, size=count) * np.log(hi / lo)).astype(np.int64)
+    fleet = []
+    t0 = time.time()
+    for j, n in enumerate(sizes):
+        keys = K.u64_keys(int(n), seed=1000 + j)
+        b = P.build_u64(keys, index_bits=32, threads=threads)
+        fleet.append((keys, P.Mphf.from_built(b)))
+    log(f"[serve] built {count} MPHFs, {int(sizes.sum())} keys in {time.time() - t0:.1f}s")
+    return fleet
+
+
+def make_requests(fleet, count, seed=6, max_size=65536):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        j = int(rng.integers(len(fleet)))
+        keys, m = fleet[j]
+        size = min(max_size, max(1, int(np.exp(rng.uniform(0, np.log(max_size))))))
+        q = keys[rng.integers(0, len(keys), size=size)]
+        reqs.append((m, q, np.zeros(size, dtype=np.uint32)))
+    return reqs
+
+
+def poisson_arrivals(count, rate_per_s, seed):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1e6 / rate_per_s, size=count))  # microseconds
+
+
+def run_server(srv, reqs, arrivals):
+    srv.reset_stats()
+    span = srv.replay([(m, q, o, t) for (m, q, o), t in zip(reqs, arrivals)])
+    st = srv.stats()
+    keys = sum(len(q) for _, q, _ in reqs)
+    return {"requests": len(reqs), "keys": keys, "makespan_s": span, "req_per_s": len(reqs) / span,
+            "keys_per_s": keys / span, "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
+            "launches": st["launches"]}
+
+
+def run_plain_baseline(reqs, torch):
+    """One plain one-key-per-lane launch per request, back to back."""
+    lat = []
+    outs = []
+    t0 = time.perf_counter()
+    for m, q, _ in reqs:
+        a = time.perf_counter()
+        m.set_kernel(P.KERNEL_PLAIN, 1, 256)
+        qt = torch.from_numpy(q.view(np.int64)).to("cuda", non_blocking=False)
+        o = m.query(qt)
+        oh = o.cpu().numpy()
+        lat.append((time.perf_counter() - a) * 1e6)
+        outs.append(oh.view(np.uint32))
+        m.set_kernel(P.KERNEL_PIPELINED, 4, 256)
+    span = time.perf_counter() - t0
+    keys = sum(len(q) for _, q, _ in reqs)
+    lat = np.array(lat)
+    return {"requests": len(reqs), "keys": keys, "makespan_s": span, "req_per_s": len(reqs) / span,
+            "keys_per_s": keys / span, "p50_us": float(np.percentile(lat, 50)),
+            "p99_us": float(np.percentile(lat, 99))}, outs
+
+
+def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), streams=2, threads=0, log=print):
+    fleet = build_fleet(threads=threads, log=log)
+    reqs = make_requests(fleet, n_requests)
+    srv = P.Server(streams=streams, max_batches=1024, slot_keys=1 << 22, max_queued_keys=1 << 31)
+    # warm up, then the saturated rate: everything queued at t = 0
+    run_server(srv, reqs[:500], np.zeros(500))
+    sat = run_server(srv, reqs, np.zeros(len(reqs)))
+    log(f"[serve] saturated: {sat['req_per_s']:.0f} req/s, {sat['keys_per_s'] / 1e9:.2f} G keys/s")
+    runs = []
+    for i, f in enumerate(loads):
+        rate = f * sat["req_per_s"]
+        arr = poisson_arrivals(len(reqs), rate, seed=100 + i)
+        r = run_server(srv, reqs, arr)
+        r["offered_fraction"] = f
+        r["offered_req_per_s"] = rate
+        runs.append(r)
+        log(f"[serve] load {f:.2f}: {r['req_per_s']:.0f} req/s p50 {r['p50_us']:.0f}us p99 {r['p99_us']:.0f}us")
+    srv.close()
+    served = [o.copy() for _, _, o in reqs]
+    base, base_out = run_plain_baseline(reqs[:2000], torch)
+    agree = all(np.array_equal(a, b) for a, b in zip(served[:2000], base_out))
+    log(f"[serve] plain per-request baseline: {base['req_per_s']:.0f} req/s p50 {base['p50_us']:.0f}us "
+        f"agree={agree}")
+    return {"saturated": sat, "open_loop": runs, "plain_per_request": base, "served_equals_plain": agree,
+            "mphfs": len(fleet), "resident_keys": int(sum(len(k) for k, _ in fleet)), "streams": streams}

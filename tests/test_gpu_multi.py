@@ -1,0 +1,168 @@
+"""GPU parity of the many-MPHF launch (row A8): each batch of a persistent
+multi-batch launch equals the oracle's query of its own MPHF, for mixes of
+sizes, key kinds and output widths, and a captured HIP graph of a plan
+replays correctly over rewritten batch tables."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_15539_amd import keygen as K
+from paper_2502_15539_amd import ptrhash as P
+
+from .mphf_pairs import load
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_pool = None
+
+
+def pool():
+    """A dozen oracle-built MPHFs of uneven sizes: u64 (u32 and u64 outputs,
+    CacheLineEF / u32 / no remap) and byte keys."""
+    global _pool
+    if _pool is None:
+        rng = np.random.default_rng(5)
+        items = []
+        for j, n in enumerate([1, 17, 1000, 4096, 10_000, 33_333, 100_000, 250_000]):
+            keys = K.u64_keys(n, seed=500 + j)
+            m = O.build_u64(keys, seed=j % 3)
+            remap = [P.REMAP_CLEF, P.REMAP_U32, P.REMAP_NONE][j % 3]
+            bits = 64 if j % 2 else 32
+            items.append(("u64", keys, m, load(m, remap, bits), remap, bits))
+        for j, n in enumerate([3, 2000, 40_000]):
+            data, off = K.strings(n, seed=900 + j)
+            m = O.build_bytes(data, off)
+            items.append(("bytes", (data, off), m, load(m, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES), P.REMAP_CLEF, 32))
+        _pool = (items, rng)
+    return _pool
+
+
+def make_batch(item, rng, size):
+    kind, keys, m, g, remap, bits = item
+    if kind == "u64":
+        nk = len(keys)
+        idx = rng.integers(0, nk, size=size)
+        q = keys[idx] if size else keys[:0]
+        if size > 4:
+            q = q.copy()
+            q[::5] = K.nonmember_keys(len(q[::5]), seed=int(rng.integers(1 << 30)))
+        want = O.query_u64(m, q, {P.REMAP_CLEF: O.REMAP_CLEF, P.REMAP_U32: O.REMAP_PLAIN,
+                                  P.REMAP_NONE: O.REMAP_NONE}[remap])
+        qt = torch.from_numpy(q.view(np.int64).copy()).to(DEV)
+        dt = torch.int64 if bits == 64 else torch.int32
+        return g, qt, torch.full((size,), -1, dtype=dt, device=DEV), want
+    data, off = keys
+    nk = len(off) - 1
+    idx = rng.integers(0, nk, size=size)
+    strs = [data[off[i]:off[i + 1]].tobytes() for i in idx]
+    buf = np.frombuffer(b"".join(strs) + b"\0" * 64, dtype=np.uint8).copy()
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in strs])]).astype(np.uint64)
+    want = O.query_bytes(m, buf, offs)
+    pair = (torch.from_numpy(buf).to(DEV), torch.from_numpy(offs.view(np.int64)).to(DEV))
+    return g, pair, torch.full((size,), -1, dtype=torch.int32, device=DEV), want
+
+
+def host(out, bits):
+    o = out.cpu().numpy()
+    return o.view(np.uint64) if out.dtype == torch.int64 else o.view(np.uint32).astype(np.uint64)
+
+
+def test_multi_matches_oracle_mixed_batches():
+    items, rng = pool()
+    for rep in range(3):
+        sizes = [int(x) for x in np.exp(rng.uniform(0, np.log(70_000), size=40)).astype(int)]
+        sizes[0] = 0
+        sizes[1] = 1
+        batches, wants = [], []
+        for s in sizes:
+            it = items[int(rng.integers(len(items)))]
+            g, q, out, want = make_batch(it, rng, s)
+            batches.append((g, q, out))
+            wants.append(want)
+        say(f"[multi] rep={rep} batches={len(batches)} keys={sum(sizes)}")
+        P.query_multi(batches)
+        torch.cuda.synchronize()
+        for (g, q, out), want in zip(batches, wants):
+            assert np.array_equal(host(out, 0), want)
+
+
+def test_multi_equals_single_calls_many_launches():
+    """Back-to-back multi launches (ring reuse) equal single queries."""
+    items, rng = pool()
+    u64_items = [it for it in items if it[0] == "u64"]
+    outs = []
+    for launch in range(20):
+        batches = []
+        for b in range(8):
+            it = u64_items[(launch + b) % len(u64_items)]
+            g, q, out, want = make_batch(it, rng, int(rng.integers(1, 5000)))
+            batches.append((g, q, out, want))
+        P.query_multi([(g, q, o) for g, q, o, _ in batches])
+        outs.extend(batches)
+    torch.cuda.synchronize()
+    say(f"[multi] ring reuse: {len(outs)} batches")
+    for g, q, out, want in outs:
+        assert np.array_equal(host(out, 0), want)
+
+
+def test_multi_errors():
+    items, rng = pool()
+    g = items[2][3]
+    q = torch.zeros(10, dtype=torch.int64, device=DEV)
+    with pytest.raises(P.PtrHashError) as e:
+        P.query_multi([(P.Mphf(), q, q)])
+    assert e.value.code == P.E_STATE
+    with pytest.raises(P.PtrHashError) as e:
+        P.query_multi([(g, q, None)])
+    assert e.value.code == P.E_INVAL
+    plan = P.MultiPlan(2)
+    with pytest.raises(P.PtrHashError) as e:
+        plan.set([(g, q, q)] * 3)
+    assert e.value.code == P.E_RANGE
+    P.query_multi([])  # nothing to do
+
+
+def test_plan_graph_capture_and_replay():
+    """Capture one plan launch; rewrite its batches between replays (with
+    eager work and syncs in between) and check every replay."""
+    items, rng = pool()
+    plan = P.MultiPlan(16)
+    stream = torch.cuda.Stream()
+    u64_items = [it for it in items if it[0] == "u64"]
+
+    def fresh():
+        bs = []
+        for b in range(int(rng.integers(1, 16))):
+            it = u64_items[int(rng.integers(len(u64_items)))]
+            bs.append(make_batch(it, rng, int(rng.integers(0, 20_000))))
+        return bs
+
+    first = fresh()
+    plan.set([(g, q, o) for g, q, o, _ in first])
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    for rep in range(6):
+        bs = first if rep == 0 else fresh()
+        plan.set([(g, q, o) for g, q, o, _ in bs])
+        say(f"[graph] replay {rep} batches={len(bs)}")
+        graph.replay()
+        torch.cuda.synchronize()
+        for g, q, out, want in bs:
+            assert np.array_equal(host(out, 0), want)
+        # eager work between replays
+        x = torch.arange(1000, device=DEV).sum()
+        assert int(x) == 499500
+    plan.close()

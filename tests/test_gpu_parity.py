@@ -206,3 +206,16 @@ def test_full_size_properties(n):
     o = g.query(nm)
     torch.cuda.synchronize()
     assert int(o.long().max()) < n
+
+
+def test_device_string_generator_matches_host():
+    n = 5000
+    say("[gen] device strings vs host")
+    d, o = P.gen_strings(n, 7)
+    hd, ho = K.strings(n, seed=7)
+    assert np.array_equal(o.cpu().numpy().view(np.uint64), ho)
+    assert np.array_equal(d.cpu().numpy()[: int(ho[-1])], hd[: int(ho[-1])])
+    qd, qo = P.gen_strings(n, 7, K.ORDER_SEED, shuffled=True)
+    hqd, hqo = K.string_query_stream(n, seed=7, order_seed=K.ORDER_SEED)
+    assert np.array_equal(qo.cpu().numpy().view(np.uint64), hqo)
+    assert np.array_equal(qd.cpu().numpy()[: int(hqo[-1])], hqd[: int(hqo[-1])])
