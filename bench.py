@@ -33,6 +33,12 @@ WORKLOADS = {
     "u64_1e9": (10**9, "u64", 64, "n=1e9 distinct uniform u64 keys (SplitMix64), shuffled stream of all 1e9 "
                                   "members, u64 indices, Default params (gamma_3, lambda=3.5, alpha=0.99, "
                                   "CacheLineEF remap)"),
+    "u64_1e9_fast": (10**9, "u64", 64, "n=1e9 distinct uniform u64 keys, shuffled stream of all members, u64 "
+                                       "indices, Fast params (gamma_1, lambda=3.0, alpha=0.99, plain u32 remap)"),
+    "u64_1e9_compact": (10**9, "u64", 64, "n=1e9 distinct uniform u64 keys, shuffled stream of all members, u64 "
+                                          "indices, Compact params (gamma_3, lambda=4.0, alpha=0.99, CacheLineEF)"),
+    "u64_1e9_phf": (10**9, "u64", 64, "n=1e9 distinct uniform u64 keys, shuffled stream of all members, u64 "
+                                      "slots (non-minimal: no remap), Default params"),
     "u64_1e8": (10**8, "u64", 32, "n=1e8 distinct uniform u64 keys, shuffled stream of all members, u32 indices, "
                                   "Default params"),
     "u64_1e6": (10**6, "u64", 32, "n=1e6 distinct uniform u64 keys, shuffled stream of all members, u32 indices, "
@@ -79,24 +85,25 @@ def time_launches(torch, fn, steps, warmup):
 
 
 def kernel_candidates(P, spec, bytes_keys=False):
+    from paper_2502_15539_amd import autotune
+
     if spec == "plain":
-        return [(P.KERNEL_PLAIN, 1, 256)]
+        return [(P.KERNEL_PLAIN, 1, 256, 0)]
     if spec != "auto":
         kk, bb = (int(x) for x in spec.split(","))
-        return [(P.KERNEL_PIPELINED, kk, bb)]
-    ks = (1, 2, 4, 8) if bytes_keys else (1, 2, 4, 8, 16)
-    return [(P.KERNEL_PLAIN, 1, 256)] + [(P.KERNEL_PIPELINED, k, b) for k in ks for b in (128, 256, 512)]
+        return [(P.KERNEL_PIPELINED, kk, bb, 0)]
+    return autotune.candidates(kpls=(1, 2, 4, 8) if bytes_keys else (1, 2, 4, 8, 16))
 
 
-def tune_and_time(torch, P, mphf, run, args, bytes_keys=False):
-    """Sweep the kernel choice, then time exactly args.steps launches."""
-    sweep = {}
-    for c in kernel_candidates(P, args.kernel, bytes_keys):
-        mphf.set_kernel(*c)
-        sweep[c] = time_launches(torch, run, 3, 1)
-    best = min(sweep, key=sweep.get)
-    mphf.set_kernel(*best)
-    log("[bench] sweep: " + ", ".join(f"{c[0]}/{c[1]}/{c[2]}={v:.3f}ms" for c, v in sorted(sweep.items())))
+def tune_and_time(torch, P, mphf, run, args, n_q, bytes_keys=False):
+    """Autotune the kernel choice (keys per lane, block, occupancy cap), then
+    time exactly args.steps launches."""
+    from paper_2502_15539_amd import autotune
+
+    best, sweep = autotune.tune(torch, mphf, run, n_q, cands=kernel_candidates(P, args.kernel, bytes_keys),
+                                use_cache=False)
+    log("[bench] sweep (kernel/keys-per-lane/block/occupancy): " +
+        ", ".join(f"{c[0]}/{c[1]}/{c[2]}/{c[3]}={v:.3f}ms" for c, v in sorted(sweep.items())))
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -120,7 +127,10 @@ def bijective(torch, out, n):
 
 
 def kernel_name(P, best):
-    return "plain" if best[0] == P.KERNEL_PLAIN else f"pipelined(keys_per_lane={best[1]},block={best[2]})"
+    if best[0] == P.KERNEL_PLAIN:
+        return "plain"
+    occ = f",blocks_per_cu<={best[3]}" if best[3] else ""
+    return f"pipelined(keys_per_lane={best[1]},block={best[2]}{occ})"
 
 
 def record(args, n, ms, wall, desc, extra_config, dtype, per_key, **fields):
@@ -168,9 +178,14 @@ def run_u64(args, torch, K, P):
     t0 = time.time()
     keys = K.u64_keys(n)
     t1 = time.time()
-    built = P.build_u64(keys, index_bits=bits, threads=threads)
+    preset = {"u64_1e9_fast": P.PRESET_FAST, "u64_1e9_compact": P.PRESET_COMPACT}.get(args.workload,
+                                                                                      P.PRESET_DEFAULT)
+    built = P.build_u64(keys, index_bits=bits, threads=threads, preset=preset)
     t2 = time.time()
     del keys
+    if args.workload == "u64_1e9_phf":  # same pilots, queried without the remap
+        built.params.remap_kind = P.REMAP_NONE
+        built.remap = np.zeros(0, dtype=np.uint8)
     p = built.params
     log(f"[bench] keygen {t1 - t0:.1f}s build {t2 - t1:.1f}s  P={p.num_parts} S=2^{p.log2_slots} "
         f"B={p.buckets_per_part} bits/key={built.bits_per_key:.3f} evictions={built.info.evictions}")
@@ -181,8 +196,8 @@ def run_u64(args, torch, K, P):
     out = torch.empty(n, dtype=torch.int64 if bits == 64 else torch.int32, device=dev)
     torch.cuda.synchronize()
 
-    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_into(q, out), args)
-    bij = bijective(torch, out, n)
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_into(q, out), args, n)
+    bij = bijective(torch, out, n) if p.remap_kind != P.REMAP_NONE else bool(int(out.max()) < p.num_parts << p.log2_slots)
     rfrac = remap_fraction(torch, P, p, built.pilots, queries=q)
 
     # roofline microbenchmarks on the same key stream
@@ -200,7 +215,7 @@ def run_u64(args, torch, K, P):
         f"bijective={bij} remap_frac={rfrac:.5f}")
 
     cpu = None
-    if args.cpu_sample:
+    if args.cpu_sample and p.remap_kind == P.REMAP_CLEF and p.gamma == P.GAMMA_CUBIC:
         from oracle import oracle as O
 
         ns = min(args.cpu_sample, n)
@@ -218,7 +233,8 @@ def run_u64(args, torch, K, P):
         log(f"[bench] cpu oracle {cdt:.1f}s for {ns} keys ({cdt / ns * 1e9:.1f} ns/key) "
             f"matches_gpu={cpu['matches_gpu']}")
 
-    per_key = 8 + bits // 8 + 1 + rfrac * 64
+    remap_line = {P.REMAP_CLEF: 64, P.REMAP_U32: 4, P.REMAP_NONE: 0}[p.remap_kind]
+    per_key = 8 + bits // 8 + 1 + rfrac * remap_line
     rec = record(args, n, ms, wall, desc,
                  {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
                   "log2_slots": p.log2_slots, "buckets_per_part": p.buckets_per_part,
@@ -228,7 +244,7 @@ def run_u64(args, torch, K, P):
                  gather_roofline={"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
                                   "block": gbest[1], "table_bytes": p.num_parts * p.buckets_per_part},
                  stream_copy_ms=copy_ms,
-                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256)),
+                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  cpu_baseline=cpu,
                  parity={"bijective_members": bij, "remap_fraction": rfrac},
                  build_s=t2 - t1,
@@ -259,7 +275,7 @@ def run_bytes(args, torch, K, P):
     qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_bytes_into(qd, qo, out), args,
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_bytes_into(qd, qo, out), args, n,
                                           bytes_keys=True)
     bij = bijective(torch, out, n)
     rfrac = remap_fraction(torch, P, p, built.pilots, data=qd, offsets=qo)
@@ -269,7 +285,7 @@ def run_bytes(args, torch, K, P):
                  {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
                   "bits_per_key": round(built.bits_per_key, 4), "mean_key_bytes": total_bytes / n},
                  "u64", per_key,
-                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256)),
+                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
                  paper_cpu_context_ns_per_key={"default_clef_loop": 37, "default_clef_stream": 23})
     rec["metric"] = "queries/s (ns/key) at n=3e8 byte-string keys"

@@ -53,17 +53,26 @@ enum { PTRHASH_GAMMA_CUBIC = 0, PTRHASH_GAMMA_LINEAR = 1 };
 /* Remap encoding for slots >= n (Section 3.4): CacheLineEF lines, a plain
  * u32 array, or none (a non-minimal perfect hash that returns the slot). */
 enum { PTRHASH_REMAP_CLEF = 0, PTRHASH_REMAP_U32 = 1, PTRHASH_REMAP_NONE = 2 };
+/* reduce(x, S) (Section 3.1, "The reduce function"): hi(C*x) mod S with S a
+ * power of two, or x mod S with one part whose S is not a power of two. */
+enum { PTRHASH_REDUCE_POW2 = 0, PTRHASH_REDUCE_MOD = 1 };
 /* Key type: 64-bit integers or byte strings (Section 3.1). */
 enum { PTRHASH_KEY_U64 = 0, PTRHASH_KEY_BYTES = 1 };
-/* Parameter presets (Section 4.1.2, "Recommended parameters"). */
+/* Parameter presets (Section 4.1.2, "Recommended parameters"). Or-ing in
+ * PTRHASH_PRESET_SINGLE_MOD switches inputs for which the rule gives a single
+ * part to the mod reduce with S = max(ceil(n/alpha), n+16) (plus one if that is
+ * a power of two), so small inputs keep a load near alpha. */
 enum { PTRHASH_PRESET_DEFAULT = 0, PTRHASH_PRESET_FAST = 1, PTRHASH_PRESET_COMPACT = 2 };
+enum { PTRHASH_PRESET_SINGLE_MOD = 0x100 };
 
 /*
  * Parameters of one MPHF. num_parts = P, slots per part S = 2^log2_slots,
  * buckets_per_part = B (Section 3.1). seed enters the pilot hash
  * h_p(p) = C*(p xor seed) and, for byte keys, the string hash.
  * remap_len must equal P*S - n. index_bits (32 or 64) is the width of each
- * output index. Passed by pointer and copied.
+ * output index. With reduce_kind PTRHASH_REDUCE_MOD there is one part of
+ * S = slots slots (not a power of two, below 2^32) and log2_slots is unused.
+ * Passed by pointer and copied.
  */
 typedef struct ptrhash_params {
     uint64_t n;
@@ -76,6 +85,9 @@ typedef struct ptrhash_params {
     uint64_t remap_len;   /* P*S - n */
     uint32_t key_kind;    /* PTRHASH_KEY_* */
     uint32_t index_bits;  /* 32 or 64 */
+    uint32_t reduce_kind; /* PTRHASH_REDUCE_* */
+    uint32_t pad_;
+    uint64_t slots;       /* S when reduce_kind is PTRHASH_REDUCE_MOD */
 } ptrhash_params;
 
 typedef struct ptrhash_handle ptrhash_handle;
@@ -192,12 +204,17 @@ PTRHASH_API int ptrhash_multi_max(void);
 /* streams: launch slots in flight at once (1..16); max_batches: requests per
  * launch (1..ptrhash_multi_max()); slot_keys: keys one launch can hold (its
  * device arena; also the largest request); max_queued_keys: admission limit
- * of keys waiting for a slot (submit returns E_RANGE beyond it). */
+ * of keys waiting for a slot (submit returns E_RANGE beyond it);
+ * copy_threads: extra host threads for the copies into and out of the
+ * pinned staging buffers; zero_copy: see the field. */
 typedef struct ptrhash_server_config {
     int streams;
     int max_batches;
     uint64_t slot_keys;
     uint64_t max_queued_keys;
+    int copy_threads;     /* host threads helping with key/index copies (0..64) */
+    int zero_copy;        /* 1: kernels read keys and write indices in mapped host memory;
+                             0: keys and indices are copied to/from device arenas */
 } ptrhash_server_config;
 
 typedef struct ptrhash_server_metrics {
@@ -206,6 +223,7 @@ typedef struct ptrhash_server_metrics {
     uint64_t keys;        /* keys answered */
     uint64_t queued;      /* requests waiting for a slot now */
     double p50_us, p99_us, max_us;  /* submit -> indices delivered */
+    double wait_p50_us, wait_p99_us; /* submit -> launch enqueued (queueing + copy-in) */
 } ptrhash_server_metrics;
 
 /* One request of a replayed arrival schedule (host keys and output). */
@@ -252,6 +270,13 @@ PTRHASH_API int ptrhash_server_destroy(ptrhash_server *srv);
  * keys_per_lane in {1, 2, 4, 8, 16}. Errors: E_INVAL. */
 enum { PTRHASH_KERNEL_PLAIN = 0, PTRHASH_KERNEL_PIPELINED = 1 };
 PTRHASH_API int ptrhash_set_kernel(ptrhash_handle *h, int kernel, int keys_per_lane, int block);
+
+/* Occupancy cap for a handle's queries: reserve LDS so that at most
+ * blocks_per_cu workgroups of the query kernel are resident on a compute
+ * unit (0 = no cap). *effective (may be NULL) receives the cap the device's
+ * LDS limits allow. Used by the autotuner together with keys_per_lane (loads
+ * in flight per lane) and block. Errors: E_INVAL, E_HIP. */
+PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int *effective);
 
 /* Message of the calling thread's last failure ("" if none). */
 PTRHASH_API const char *ptrhash_last_error(void);

@@ -28,6 +28,9 @@ extern "C" {
 
 enum { ORC_GAMMA_CUBIC = 0, ORC_GAMMA_LINEAR = 1 };
 enum { ORC_REMAP_CLEF = 0, ORC_REMAP_PLAIN = 1, ORC_REMAP_NONE = 2 };
+/* reduce(x, S): hi(C*x) mod S with S a power of two, or x mod S with S not a
+ * power of two and a single part ("The reduce function", Section 3.1). */
+enum { ORC_REDUCE_POW2 = 0, ORC_REDUCE_MOD = 1 };
 
 enum {
     ORC_OK = 0,
@@ -43,12 +46,12 @@ enum {
 typedef struct {
     uint64_t n;                /* number of keys */
     uint64_t num_parts;        /* P */
-    uint64_t slots_per_part;   /* S = 2^log2_slots */
+    uint64_t slots_per_part;   /* S (2^log2_slots unless reduce_kind is MOD) */
     uint32_t log2_slots;
     uint32_t buckets_per_part; /* B */
     uint64_t seed;             /* pilot-hash seed (and byte-hash seed) */
     int32_t gamma;             /* ORC_GAMMA_* */
-    int32_t pad_;
+    int32_t reduce_kind;       /* ORC_REDUCE_* */
     uint64_t remap_len;        /* P*S - n, entries of the remap table F */
 } orc_params;
 
@@ -74,6 +77,12 @@ int orc_params_for(uint64_t n, double alpha, double lambda, int32_t gamma,
                    uint32_t log2_slots_override, uint64_t seed, orc_params *out);
 int orc_params_explicit(uint64_t n, uint64_t P, uint32_t log2_slots, uint32_t B,
                         int32_t gamma, uint64_t seed, orc_params *out);
+/* One part of S slots (S not a power of two) with reduce(x, S) = x mod S. */
+int orc_params_single_mod(uint64_t n, uint64_t S, uint32_t B, int32_t gamma, uint64_t seed, orc_params *out);
+/* The rule for a single part with the mod reduce: S = max(ceil(n/alpha), n+16),
+ * plus one if that is a power of two; B = ceil(alpha*S/lambda). */
+int orc_params_for_single_mod(uint64_t n, double alpha, double lambda, int32_t gamma, uint64_t seed,
+                              orc_params *out);
 
 uint64_t orc_hash_u64(uint64_t key);
 uint64_t orc_fmix64(uint64_t k);
@@ -85,6 +94,7 @@ uint64_t orc_gamma(int32_t kind, uint64_t x);
 uint64_t orc_bucket(const orc_params *p, uint64_t h);
 uint64_t orc_hp(uint64_t seed, uint32_t pilot);
 uint64_t orc_reduce(uint64_t x, uint64_t S);
+uint64_t orc_reduce_mod(uint64_t x, uint64_t S);
 uint64_t orc_slot(const orc_params *p, uint64_t h, uint32_t pilot);
 
 /* Construction (Section 3.2). pilots: P*B bytes; F: remap_len u64 entries.

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libptrhash_oracle.so")
 
 GAMMA_CUBIC, GAMMA_LINEAR = 0, 1
 REMAP_CLEF, REMAP_PLAIN, REMAP_NONE = 0, 1, 2
+REDUCE_POW2, REDUCE_MOD = 0, 1
 OK, EINVAL, EDUPLICATE, EPART_OVERFLOW, EBUILD_FAILED, ECLEF_RANGE, ENOMEM = range(7)
 
 #: Default parameters (Section 4.1.2, "Recommended parameters": Default).
@@ -41,12 +42,12 @@ class Params(C.Structure):
         ("buckets_per_part", C.c_uint32),
         ("seed", C.c_uint64),
         ("gamma", C.c_int32),
-        ("pad_", C.c_int32),
+        ("reduce_kind", C.c_int32),
         ("remap_len", C.c_uint64),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class BuildCfg(C.Structure):
@@ -78,6 +79,9 @@ def lib():
             "orc_lo": (u64, [u64, u64]),
             "orc_params_for": (C.c_int, [u64, C.c_double, C.c_double, C.c_int32, C.c_uint32, u64, P(Params)]),
             "orc_params_explicit": (C.c_int, [u64, u64, C.c_uint32, C.c_uint32, C.c_int32, u64, P(Params)]),
+            "orc_params_single_mod": (C.c_int, [u64, u64, C.c_uint32, C.c_int32, u64, P(Params)]),
+            "orc_params_for_single_mod": (C.c_int, [u64, C.c_double, C.c_double, C.c_int32, u64, P(Params)]),
+            "orc_reduce_mod": (u64, [u64, u64]),
             "orc_hash_u64": (u64, [u64]),
             "orc_fmix64": (u64, [u64]),
             "orc_hash_bytes": (u64, [u64, C.c_void_p, u64]),
@@ -124,6 +128,18 @@ def params_explicit(n, P, log2_slots, B, gamma=GAMMA_CUBIC, seed=0) -> Params:
     rc = lib().orc_params_explicit(int(n), int(P), int(log2_slots), int(B), int(gamma), int(seed), C.byref(p))
     if rc:
         raise ValueError(f"orc_params_explicit -> {rc}")
+    return p
+
+
+def params_single_mod(n, S=None, B=None, alpha=ALPHA, lam=LAMBDA, gamma=GAMMA_CUBIC, seed=0) -> Params:
+    """Single part with reduce = x mod S; S and B from the rule unless given."""
+    p = Params()
+    if S is None:
+        rc = lib().orc_params_for_single_mod(int(n), float(alpha), float(lam), int(gamma), int(seed), C.byref(p))
+    else:
+        rc = lib().orc_params_single_mod(int(n), int(S), int(B), int(gamma), int(seed), C.byref(p))
+    if rc:
+        raise ValueError(f"single-part mod params(n={n}) -> {rc}")
     return p
 
 

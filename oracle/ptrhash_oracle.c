@@ -87,6 +87,41 @@ int orc_params_explicit(uint64_t n, uint64_t P, uint32_t log2_slots, uint32_t B,
     return ORC_OK;
 }
 
+/*
+ * reading: the fast-mod variant ("The reduce function"): a single part whose
+ * S is not a power of two, so that x mod S depends on every bit of x.
+ */
+int orc_params_single_mod(uint64_t n, uint64_t S, uint32_t B, int32_t gamma, uint64_t seed, orc_params *out)
+{
+    if (!out || n == 0 || B == 0 || S < n || S < 2 || (S & (S - 1)) == 0 || S > (1ULL << 40)) return ORC_EINVAL;
+    if (gamma != ORC_GAMMA_CUBIC && gamma != ORC_GAMMA_LINEAR) return ORC_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->n = n;
+    out->num_parts = 1;
+    out->slots_per_part = S;
+    out->log2_slots = 0;
+    out->buckets_per_part = B;
+    out->seed = seed;
+    out->gamma = gamma;
+    out->reduce_kind = ORC_REDUCE_MOD;
+    out->remap_len = S - n;
+    return ORC_OK;
+}
+
+int orc_params_for_single_mod(uint64_t n, double alpha, double lambda, int32_t gamma, uint64_t seed,
+                              orc_params *out)
+{
+    if (!out || n == 0 || !(alpha > 0.0 && alpha <= 1.0) || !(lambda > 0.0)) return ORC_EINVAL;
+    /* reading: at least 16 free slots, so that tiny inputs still build */
+    uint64_t S = (uint64_t)ceil((double)n / alpha);
+    if (S < n + 16) S = n + 16;
+    if ((S & (S - 1)) == 0) S++;
+    uint64_t B = (uint64_t)ceil(alpha * (double)S / lambda);
+    if (B < 1) B = 1;
+    if (B > 0xFFFFFFFFULL) return ORC_EINVAL;
+    return orc_params_single_mod(n, S, (uint32_t)B, gamma, seed, out);
+}
+
 /* ---- Key hashes (Section 3.1, "Hash functions") ---- */
 
 /* Integer keys: h(k) = C*k, invertible modulo 2^64 because C is odd. */
@@ -167,11 +202,19 @@ uint64_t orc_hp(uint64_t seed, uint32_t pilot) { return ORC_C * ((uint64_t)pilot
 /* reduce(x, S) = hi(C*x) mod S for S a power of two. */
 uint64_t orc_reduce(uint64_t x, uint64_t S) { return orc_hi(ORC_C, x) & (S - 1); }
 
+/* reduce(x, S) = x mod S (S not a power of two, single part). */
+uint64_t orc_reduce_mod(uint64_t x, uint64_t S) { return x % S; }
+
+static uint64_t reduce_of(const orc_params *p, uint64_t x)
+{
+    return p->reduce_kind == ORC_REDUCE_MOD ? orc_reduce_mod(x, p->slots_per_part)
+                                            : orc_reduce(x, p->slots_per_part);
+}
+
 /* slot(k) = part(k)*S + reduce(h(k) xor h_p(p_bucket(k)), S). */
 uint64_t orc_slot(const orc_params *p, uint64_t h, uint32_t pilot)
 {
-    return orc_part(p, h) * p->slots_per_part +
-           orc_reduce(h ^ orc_hp(p->seed, pilot), p->slots_per_part);
+    return orc_part(p, h) * p->slots_per_part + reduce_of(p, h ^ orc_hp(p->seed, pilot));
 }
 
 /* ---- CacheLineEF (Section 3.4, eq. clef) ---- */
@@ -365,8 +408,7 @@ static uint64_t bucket_slots(part_ctx *c, uint64_t part, uint32_t b, uint32_t pi
     uint64_t g = part * c->p->buckets_per_part + b;
     uint64_t s = c->start[g + 1] - c->start[g];
     for (uint64_t j = 0; j < s; j++)
-        slots[j] = orc_reduce(c->h[c->order[c->start[g] + j]] ^ orc_hp(c->p->seed, pilot),
-                              c->p->slots_per_part);
+        slots[j] = reduce_of(c->p, c->h[c->order[c->start[g] + j]] ^ orc_hp(c->p->seed, pilot));
     return s;
 }
 

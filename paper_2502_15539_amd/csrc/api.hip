@@ -84,6 +84,11 @@ DevMphf device_view(const ptrhash_handle *h) {
     m.log2_slots = h->params.log2_slots;
     m.gamma = h->params.gamma;
     m.remap_kind = h->params.remap_kind;
+    m.reduce_kind = h->params.reduce_kind;
+    if (h->params.reduce_kind == PTRHASH_REDUCE_MOD) {
+        m.mod_slots = (uint32_t)h->params.slots;
+        m.mod_magic = ~0ull / h->params.slots;  // = floor(2^64/S) since S is not a power of two
+    }
     return m;
 }
 
@@ -95,8 +100,17 @@ int check_params(const ptrhash_params *p) {
     if (p->num_parts == 0 || p->num_parts > 0xffffffffull)
         return fail(PTRHASH_E_INVAL, "num_parts must be in [1, 2^32)");
     if (p->buckets_per_part == 0) return fail(PTRHASH_E_INVAL, "buckets_per_part must be positive");
-    if (p->log2_slots > 40) return fail(PTRHASH_E_RANGE, "log2_slots %u > 40", p->log2_slots);
-    const uint64_t S = 1ull << p->log2_slots;
+    if (p->reduce_kind > PTRHASH_REDUCE_MOD) return fail(PTRHASH_E_INVAL, "unknown reduce_kind %u", p->reduce_kind);
+    uint64_t S;
+    if (p->reduce_kind == PTRHASH_REDUCE_MOD) {
+        if (p->num_parts != 1) return fail(PTRHASH_E_INVAL, "the mod reduce needs a single part");
+        if (p->slots < 2 || p->slots >= (1ull << 32) || (p->slots & (p->slots - 1)) == 0)
+            return fail(PTRHASH_E_INVAL, "the mod reduce needs 2 <= S < 2^32, S not a power of two");
+        S = p->slots;
+    } else {
+        if (p->log2_slots > 40) return fail(PTRHASH_E_RANGE, "log2_slots %u > 40", p->log2_slots);
+        S = 1ull << p->log2_slots;
+    }
     if (p->num_parts > kMaxIndexSpace / S) return fail(PTRHASH_E_RANGE, "P*S >= 2^40");
     if (p->num_parts * (uint64_t)p->buckets_per_part > kMaxIndexSpace) return fail(PTRHASH_E_RANGE, "P*B > 2^40");
     if (p->num_parts * S < p->n) return fail(PTRHASH_E_INVAL, "P*S < n");
@@ -118,6 +132,52 @@ int check_params(const ptrhash_params *p) {
 }  // namespace
 
 namespace ptrhash {
+int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k) {
+    // validate everything before touching the table
+    for (int i = 0; i < k; ++i) {
+        const ptrhash_query_desc &d = descs[i];
+        if (!d.handle) return fail(PTRHASH_E_INVAL, "batch %d: handle is NULL", i);
+        if (!d.handle->loaded) return fail(PTRHASH_E_STATE, "batch %d: handle has no MPHF loaded", i);
+        if (d.n_q == 0) continue;
+        if (!d.out) return fail(PTRHASH_E_INVAL, "batch %d: out is NULL", i);
+        if (d.handle->params.key_kind == PTRHASH_KEY_U64) {
+            if (!d.keys) return fail(PTRHASH_E_INVAL, "batch %d: keys is NULL for a u64-key MPHF", i);
+        } else {
+            if (!d.data || !d.offsets) return fail(PTRHASH_E_INVAL, "batch %d: data/offsets is NULL", i);
+            if (reinterpret_cast<uintptr_t>(d.data) & 7u)
+                return fail(PTRHASH_E_INVAL, "batch %d: data must be 8-byte aligned", i);
+        }
+    }
+    uint32_t c = 0;
+    uint64_t tiles = 0;
+    for (int i = 0; i < k; ++i) {
+        const ptrhash_query_desc &d = descs[i];
+        if (d.n_q == 0) continue;
+        MultiDesc &m = t->descs[c++];
+        m.m = device_view(d.handle);
+        m.bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
+        m.out64 = d.handle->params.index_bits == 64;
+        m.keys = m.bytes ? nullptr : d.keys;
+        m.data = m.bytes ? d.data : nullptr;
+        m.offsets = m.bytes ? d.offsets : nullptr;
+        m.out = d.out;
+        m.nq = d.n_q;
+        m.tile_begin = tiles;
+        tiles += (d.n_q + kMultiTile - 1) / kMultiTile;
+    }
+    t->count = c;
+    t->tiles = tiles;
+    return PTRHASH_OK;
+}
+
+uint32_t multi_grid() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 1;
+    return (uint32_t)cus * (uint32_t)multi_blocks_per_cu();
+}
+
 bool valid_tuning(int kernel, int keys_per_lane, int block) {
     if (kernel != kKernelPlain && kernel != kKernelPipelined) return false;
     if (block < 64 || block > 1024 || block % 64) return false;
@@ -152,6 +212,8 @@ PTRHASH_API int ptrhash_params_default(uint64_t n, int preset, uint32_t key_kind
     const double alpha = 0.99;
     double lambda;
     uint32_t gamma, remap;
+    const bool single_mod = (preset & PTRHASH_PRESET_SINGLE_MOD) != 0;
+    preset &= ~PTRHASH_PRESET_SINGLE_MOD;
     switch (preset) {
     case PTRHASH_PRESET_DEFAULT: lambda = 3.5; gamma = PTRHASH_GAMMA_CUBIC; remap = PTRHASH_REMAP_CLEF; break;
     case PTRHASH_PRESET_FAST: lambda = 3.0; gamma = PTRHASH_GAMMA_LINEAR; remap = PTRHASH_REMAP_U32; break;
@@ -179,6 +241,18 @@ PTRHASH_API int ptrhash_params_default(uint64_t n, int preset, uint32_t key_kind
     p.remap_len = P * S - n;
     p.key_kind = key_kind;
     p.index_bits = index_bits ? index_bits : (n <= (1ull << 32) ? 32u : 64u);
+    if (single_mod && P == 1) {
+        uint64_t Sm = (uint64_t)std::ceil((double)n / alpha);
+        if (Sm < n + 16) Sm = n + 16;  // at least 16 free slots for tiny inputs
+        if ((Sm & (Sm - 1)) == 0) ++Sm;
+        uint64_t Bm = (uint64_t)std::ceil(alpha * (double)Sm / lambda);
+        if (Bm < 1) Bm = 1;
+        p.reduce_kind = PTRHASH_REDUCE_MOD;
+        p.slots = Sm;
+        p.log2_slots = 0;
+        p.buckets_per_part = (uint32_t)Bm;
+        p.remap_len = Sm - n;
+    }
     const int rc = check_params(&p);
     if (rc) return rc;
     *out = p;
@@ -245,6 +319,27 @@ PTRHASH_API int ptrhash_set_kernel(ptrhash_handle *h, int kernel, int keys_per_l
     h->tuning.kernel = kernel;
     h->tuning.keys_per_lane = keys_per_lane;
     h->tuning.block = block;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int *effective) {
+    if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(PTRHASH_E_INVAL, "blocks_per_cu must be 0..64");
+    if (blocks_per_cu == 0) {
+        h->tuning.lds_bytes = 0;
+        if (effective) *effective = 0;
+        return PTRHASH_OK;
+    }
+    int dev = 0, per_cu = 0, per_block = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+        return hip_fail(e, "device query");
+    uint32_t bytes = (uint32_t)(per_cu / blocks_per_cu) & ~255u;
+    if (bytes > (uint32_t)per_block) bytes = (uint32_t)per_block & ~255u;
+    h->tuning.lds_bytes = bytes;
+    if (effective) *effective = bytes ? per_cu / (int)bytes : 0;
     return PTRHASH_OK;
 }
 
@@ -319,13 +414,7 @@ PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **ou
         return fail(PTRHASH_E_NOMEM, "hipHostMalloc for the staging table: %s", hipGetErrorString(e));
     }
     std::memset(p->h_stage, 0, bytes);
-    int dev = 0, cus = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess ||
-        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
-        ptrhash_multi_plan_destroy(p);
-        return hip_fail(e, "device query");
-    }
-    p->grid = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)multi_blocks_per_cu();
+    p->grid = multi_grid();
     p->used_bytes = multi_table_bytes(1);
     *out = p;
     return PTRHASH_OK;
@@ -335,41 +424,9 @@ PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_q
     if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
     if (k < 0 || (k > 0 && !descs)) return fail(PTRHASH_E_INVAL, "bad descriptor array");
     if (k > plan->max) return fail(PTRHASH_E_RANGE, "%d batches exceed the plan's %d", k, plan->max);
-    // validate everything before touching the staging table
-    for (int i = 0; i < k; ++i) {
-        const ptrhash_query_desc &d = descs[i];
-        if (!d.handle) return fail(PTRHASH_E_INVAL, "batch %d: handle is NULL", i);
-        if (!d.handle->loaded) return fail(PTRHASH_E_STATE, "batch %d: handle has no MPHF loaded", i);
-        if (d.n_q == 0) continue;
-        if (!d.out) return fail(PTRHASH_E_INVAL, "batch %d: out is NULL", i);
-        if (d.handle->params.key_kind == PTRHASH_KEY_U64) {
-            if (!d.keys) return fail(PTRHASH_E_INVAL, "batch %d: keys is NULL for a u64-key MPHF", i);
-        } else {
-            if (!d.data || !d.offsets) return fail(PTRHASH_E_INVAL, "batch %d: data/offsets is NULL", i);
-            if (reinterpret_cast<uintptr_t>(d.data) & 7u)
-                return fail(PTRHASH_E_INVAL, "batch %d: data must be 8-byte aligned", i);
-        }
-    }
-    MultiTable *t = plan->h_stage;
-    uint32_t c = 0;
-    uint64_t tiles = 0;
-    for (int i = 0; i < k; ++i) {
-        const ptrhash_query_desc &d = descs[i];
-        if (d.n_q == 0) continue;
-        MultiDesc &m = t->descs[c++];
-        m.m = device_view(d.handle);
-        m.bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
-        m.out64 = d.handle->params.index_bits == 64;
-        m.keys = m.bytes ? nullptr : d.keys;
-        m.data = m.bytes ? d.data : nullptr;
-        m.offsets = m.bytes ? d.offsets : nullptr;
-        m.out = d.out;
-        m.nq = d.n_q;
-        m.tile_begin = tiles;
-        tiles += (d.n_q + kMultiTile - 1) / kMultiTile;
-    }
-    t->count = c;
-    t->tiles = tiles;
+    const int rc = fill_multi_table(plan->h_stage, descs, k);
+    if (rc) return rc;
+    const uint32_t c = plan->h_stage->count;
     plan->used_bytes = multi_table_bytes(c ? (int)c : 1);
     return PTRHASH_OK;
 }

@@ -65,6 +65,7 @@ uint64_t hash_bytes(uint64_t seed, const uint8_t *s, uint64_t len) {
 struct Geometry {
     uint64_t n, P, S, B, seed;
     uint32_t log2S, gamma;
+    bool mod = false;  // reduce(x, S) = x mod S (one part) instead of hi(C*x) mod 2^log2S
 
     uint32_t part(uint64_t h) const { return (uint32_t)mul_hi(P, h); }
     uint32_t local_bucket(uint64_t h) const {
@@ -113,7 +114,9 @@ struct PartWorker {
         return cur;
     }
 
-    uint32_t slot(uint64_t h, uint32_t p) const { return (uint32_t)(mul_hi(kMix, h ^ hp[p]) & (geo->S - 1)); }
+    uint32_t slot(uint64_t h, uint32_t p) const {
+        return geo->mod ? (uint32_t)((h ^ hp[p]) % geo->S) : (uint32_t)(mul_hi(kMix, h ^ hp[p]) & (geo->S - 1));
+    }
 
     // Group the part's hashes by local bucket (counting sort).
     void group(const uint64_t *h, uint64_t cnt) {
@@ -349,10 +352,15 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     if (params->key_kind != (bytes ? PTRHASH_KEY_BYTES : PTRHASH_KEY_U64))
         return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
     if (params->num_parts == 0 || params->num_parts > 0xffffffffull || params->buckets_per_part == 0 ||
-        params->log2_slots > 31 || params->gamma > PTRHASH_GAMMA_LINEAR || params->remap_kind > PTRHASH_REMAP_NONE)
+        params->log2_slots > 31 || params->gamma > PTRHASH_GAMMA_LINEAR || params->remap_kind > PTRHASH_REMAP_NONE ||
+        params->reduce_kind > PTRHASH_REDUCE_MOD)
         return set_error(PTRHASH_E_INVAL, "invalid params");
-    Geometry g{n, params->num_parts, 1ull << params->log2_slots, params->buckets_per_part, params->seed,
-               params->log2_slots, params->gamma};
+    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
+    if (mod && (params->num_parts != 1 || params->slots < 2 || params->slots >= (1ull << 31) ||
+                (params->slots & (params->slots - 1)) == 0))
+        return set_error(PTRHASH_E_INVAL, "mod reduce: one part, 2 <= S < 2^31, S not a power of two");
+    Geometry g{n, params->num_parts, mod ? params->slots : 1ull << params->log2_slots, params->buckets_per_part,
+               params->seed, params->log2_slots, params->gamma, mod};
     if (g.P * g.S < n || params->remap_len != g.P * g.S - n) return set_error(PTRHASH_E_INVAL, "P*S/remap_len");
     if (g.B >= (1ull << 31)) return set_error(PTRHASH_E_RANGE, "too many buckets per part");
     const uint64_t rbytes = ptrhash_remap_bytes(params);

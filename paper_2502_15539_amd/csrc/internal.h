@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "mphf_device.h"
+#include "ptrhash.h"
 
 namespace ptrhash {
 
@@ -14,6 +15,7 @@ struct Tuning {
     int kernel = kKernelPipelined;
     int keys_per_lane = 4;
     int block = 256;
+    uint32_t lds_bytes = 0;  // dynamic LDS reserved per workgroup: caps resident workgroups per CU
 };
 
 bool valid_tuning(int kernel, int keys_per_lane, int block);
@@ -47,6 +49,9 @@ inline size_t multi_table_bytes(int max_descs) {
 
 hipError_t launch_query_multi(const MultiTable *table, uint32_t grid, hipStream_t s);
 int multi_blocks_per_cu();  // resident blocks of query_multi per compute unit
+uint32_t multi_grid();      // persistent grid size of query_multi on the current device
+// Validate k batches and write them (and the tile prefix sums) into t.
+int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k);
 
 hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
                             const Tuning &t, hipStream_t s);

@@ -173,14 +173,16 @@ static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t 
     OutT *o = static_cast<OutT *>(out);
     const uint32_t blk = (uint32_t)t.block;
     if (t.kernel == kKernelPlain) {
-        hipLaunchKernelGGL(query_plain<OutT>, dim3((uint32_t)ceil_div(nq, blk)), dim3(blk), 0, s, keys, nq, o, m);
+        hipLaunchKernelGGL(query_plain<OutT>, dim3((uint32_t)ceil_div(nq, blk)), dim3(blk), t.lds_bytes, s, keys, nq,
+                           o, m);
         return hipGetLastError();
     }
     const uint64_t grid = ceil_div(nq, (uint64_t)blk * t.keys_per_lane);
     switch (t.keys_per_lane) {
 #define PTRHASH_CASE(KK)                                                                                     \
     case KK:                                                                                                 \
-        hipLaunchKernelGGL((query_pipelined<KK, OutT>), dim3((uint32_t)grid), dim3(blk), 0, s, keys, nq, o, m); \
+        hipLaunchKernelGGL((query_pipelined<KK, OutT>), dim3((uint32_t)grid), dim3(blk), t.lds_bytes, s, keys, nq, o, \
+                           m);                                                                             \
         break;
         PTRHASH_CASE(1)
         PTRHASH_CASE(2)
@@ -209,7 +211,7 @@ static hipError_t launch_bytes_t(const DevMphf &m, const uint8_t *data, const ui
     switch (K) {
 #define PTRHASH_CASE(KK)                                                                                   \
     case KK:                                                                                               \
-        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), dim3((uint32_t)grid), dim3(blk), 0, s, data, offsets, nq, \
+        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), dim3((uint32_t)grid), dim3(blk), t.lds_bytes, s, data, offsets, nq, \
                            o, m);                                                                          \
         break;
         PTRHASH_CASE(1)

@@ -17,6 +17,7 @@ constexpr uint64_t kMix = 0x517cc1b727220a95ull;
 
 enum : uint32_t { kGammaCubic = 0, kGammaLinear = 1 };
 enum : uint32_t { kRemapClef = 0, kRemapU32 = 1, kRemapNone = 2 };
+enum : uint32_t { kReducePow2 = 0, kReduceMod = 1 };
 
 // One resident MPHF as the kernels see it (passed by value).
 struct DevMphf {
@@ -29,7 +30,9 @@ struct DevMphf {
     uint32_t log2_slots;    // S = 2^log2_slots
     uint32_t gamma;
     uint32_t remap_kind;
-    uint32_t pad_;
+    uint32_t reduce_kind;
+    uint32_t mod_slots;     // S for the mod reduce (one part)
+    uint64_t mod_magic;     // floor(2^64 / S) for the mod reduce
 };
 
 // hi and lo 64-bit halves of a (32-bit) * b (64-bit): two 32x32->64
@@ -68,9 +71,18 @@ __device__ __forceinline__ uint64_t bucket_of(const DevMphf &m, uint64_t h, uint
     return (uint64_t)part * m.buckets + b;
 }
 
-// slot = part*S + (hi(C*(h xor C*(pilot xor seed))) mod S).
+// x mod S for S < 2^32, not a power of two: q = hi(x * floor(2^64/S)) is
+// floor(x/S) or one less, so one conditional subtraction fixes the rest.
+__device__ __forceinline__ uint64_t mod_reduce(uint64_t x, uint32_t S, uint64_t magic) {
+    uint64_t r = x - mulhi64(x, magic) * S;
+    return r >= S ? r - S : r;
+}
+
+// slot = part*S + reduce(h xor C*(pilot xor seed), S) with reduce(x, S) =
+// hi(C*x) mod S (S a power of two) or x mod S (one part).
 __device__ __forceinline__ uint64_t slot_of(const DevMphf &m, uint64_t h, uint32_t part, uint32_t pilot) {
     const uint64_t hp = kMix * ((uint64_t)pilot ^ m.seed);
+    if (m.reduce_kind == kReduceMod) return mod_reduce(h ^ hp, m.mod_slots, m.mod_magic);
     const uint64_t local = mulhi64(kMix, h ^ hp) & ((1ull << m.log2_slots) - 1);
     return ((uint64_t)part << m.log2_slots) | local;
 }

@@ -40,16 +40,118 @@ struct Request {
     void *out = nullptr;
     uint32_t out_bytes = 4;   // bytes per index
     Clock::time_point t_submit{};
+    Clock::time_point t_launch{};
     uint64_t key_off = 0;     // placement inside the slot arena
     uint64_t out_off = 0;     // byte offset inside the slot's output arena
 };
 
+// Fork-join pool for the host copies of a launch (keys into pinned staging,
+// indices out of it): the copies of one launch are split into chunks that
+// the pool's threads and the dispatcher take from a shared counter.
+class CopyPool {
+  public:
+    struct Job {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+
+    explicit CopyPool(int threads) {
+        for (int i = 0; i < threads; ++i) workers_.emplace_back([this] { loop(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+
+    // Run every job; returns when all are done and no pool thread still
+    // holds the job list.
+    void run(std::vector<Job> &jobs) {
+        if (jobs.empty()) return;
+        if (workers_.empty() || jobs.size() == 1) {
+            for (const Job &j : jobs) std::memcpy(j.dst, j.src, j.bytes);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            jobs_ = &jobs;
+            next_.store(0);
+            left_.store(jobs.size());
+            ++gen_;
+        }
+        cv_.notify_all();
+        take(jobs);
+        while (left_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
+        for (;;) {  // threads join only under the lock while jobs_ is set
+            std::unique_lock<std::mutex> l(mu_);
+            if (active_.load(std::memory_order_acquire) == 0) {
+                jobs_ = nullptr;
+                return;
+            }
+            l.unlock();
+            std::this_thread::yield();
+        }
+    }
+
+  private:
+    void take(std::vector<Job> &jobs) {
+        for (;;) {
+            const size_t i = next_.fetch_add(1);
+            if (i >= jobs.size()) return;
+            const Job &j = jobs[i];
+            std::memcpy(j.dst, j.src, j.bytes);
+            left_.fetch_sub(1, std::memory_order_release);
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            std::vector<Job> *jobs;
+            {
+                std::unique_lock<std::mutex> l(mu_);
+                cv_.wait(l, [&] { return stop_ || (gen_ != seen && jobs_); });
+                if (stop_) return;
+                seen = gen_;
+                jobs = jobs_;
+                active_.fetch_add(1, std::memory_order_acq_rel);
+            }
+            take(*jobs);
+            active_.fetch_sub(1, std::memory_order_acq_rel);
+        }
+    }
+
+    std::vector<std::thread> workers_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::vector<Job> *jobs_ = nullptr;
+    std::atomic<size_t> next_{0}, left_{0};
+    std::atomic<int> active_{0};
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+// Split a copy into chunks of at most 256 KiB.
+void add_copy(std::vector<CopyPool::Job> &jobs, void *dst, const void *src, size_t bytes) {
+    constexpr size_t kChunk = 256 << 10;
+    for (size_t o = 0; o < bytes; o += kChunk)
+        jobs.push_back({static_cast<uint8_t *>(dst) + o, static_cast<const uint8_t *>(src) + o,
+                        std::min(kChunk, bytes - o)});
+}
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    ptrhash_multi_plan *plan = nullptr;
+    ptrhash_multi_plan *plan = nullptr;        // copy mode
     uint64_t *d_keys = nullptr, *h_keys = nullptr;
     uint8_t *d_out = nullptr, *h_out = nullptr;
+    ptrhash::MultiTable *h_table = nullptr;             // zero-copy mode: mapped host table
+    ptrhash::MultiTable *v_table = nullptr;             // its device address
+    uint64_t *v_keys = nullptr;                // device addresses of h_keys / h_out
+    uint8_t *v_out = nullptr;
     std::vector<Request> reqs;
     bool busy = false;
 };
@@ -67,10 +169,13 @@ struct ptrhash_server {
     std::unordered_set<uint64_t> outstanding;       // submitted, not finished
     std::unordered_map<uint64_t, double> finished;  // ticket -> latency (us), until waited for
     std::vector<double> latencies;                   // all completed requests
+    std::vector<double> waits;                       // submit -> launch enqueued
+    CopyPool *pool = nullptr;
     uint64_t launches = 0, completed = 0, keys_done = 0;
     int error = PTRHASH_OK;
     bool stop = false;
     int device = 0;
+    uint32_t grid = 0;
     std::thread worker;
 };
 
@@ -86,6 +191,7 @@ void free_slot(Slot &s) {
     if (s.d_out) (void)hipFree(s.d_out);
     if (s.h_keys) (void)hipHostFree(s.h_keys);
     if (s.h_out) (void)hipHostFree(s.h_out);
+    if (s.h_table) (void)hipHostFree(s.h_table);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     s = Slot{};
@@ -93,10 +199,13 @@ void free_slot(Slot &s) {
 
 // Retire a finished slot: copy indices to the callers' buffers.
 void retire(ptrhash_server *srv, Slot &s) {
+    std::vector<CopyPool::Job> jobs;
+    for (const Request &r : s.reqs) add_copy(jobs, r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
+    srv->pool->run(jobs);
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lock(srv->mu);
     for (const Request &r : s.reqs) {
-        std::memcpy(r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
+        srv->waits.push_back(std::chrono::duration<double, std::micro>(r.t_launch - r.t_submit).count());
         const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
         srv->outstanding.erase(r.ticket);
         srv->finished[r.ticket] = us;
@@ -127,15 +236,29 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
     if (s.reqs.empty()) return PTRHASH_OK;
     s.busy = true;
     lock.unlock();
+    const bool zc = srv->cfg.zero_copy != 0;
     std::vector<ptrhash_query_desc> descs(s.reqs.size());
+    std::vector<CopyPool::Job> jobs;
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         const Request &r = s.reqs[i];
-        std::memcpy(s.h_keys + r.key_off, r.keys, r.n_q * sizeof(uint64_t));
-        descs[i] = ptrhash_query_desc{r.handle, s.d_keys + r.key_off, nullptr, nullptr, r.n_q, s.d_out + r.out_off};
+        add_copy(jobs, s.h_keys + r.key_off, r.keys, r.n_q * sizeof(uint64_t));
+        uint64_t *k = (zc ? s.v_keys : s.d_keys) + r.key_off;
+        uint8_t *o = (zc ? s.v_out : s.d_out) + r.out_off;
+        descs[i] = ptrhash_query_desc{r.handle, k, nullptr, nullptr, r.n_q, o};
     }
-    int rc = ptrhash_multi_plan_set(s.plan, descs.data(), (int)descs.size());
+    srv->pool->run(jobs);
+    int rc;
     hipError_t e = hipSuccess;
-    if (rc == PTRHASH_OK) {
+    if (zc) {
+        // the kernel reads keys and the batch table from, and writes indices
+        // to, mapped coherent host memory: one stream operation per launch
+        rc = ptrhash::fill_multi_table(s.h_table, descs.data(), (int)descs.size());
+        if (rc == PTRHASH_OK) {
+            e = ptrhash::launch_query_multi(s.v_table, srv->grid, s.stream);
+            if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+            if (e != hipSuccess) rc = hip_err(e, "serving launch");
+        }
+    } else if ((rc = ptrhash_multi_plan_set(s.plan, descs.data(), (int)descs.size())) == PTRHASH_OK) {
         e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) rc = ptrhash_multi_plan_launch(s.plan, s.stream);
         if (e == hipSuccess && rc == PTRHASH_OK)
@@ -143,6 +266,8 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
         if (e == hipSuccess && rc == PTRHASH_OK) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) rc = hip_err(e, "serving launch");
     }
+    const auto launched = Clock::now();
+    for (Request &r : s.reqs) r.t_launch = launched;
     lock.lock();
     if (rc == PTRHASH_OK) srv->launches++;
     return rc;
@@ -150,6 +275,7 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
 
 void run(ptrhash_server *srv) {
     (void)hipSetDevice(srv->device);
+    auto idle_since = Clock::now();
     std::unique_lock<std::mutex> lock(srv->mu);
     for (;;) {
         bool any_busy = false;
@@ -183,10 +309,20 @@ void run(ptrhash_server *srv) {
             any_busy |= s.busy;
         }
         if (srv->stop && srv->queue.empty() && !any_busy) return;
-        if (any_busy)
-            srv->cv_work.wait_for(lock, std::chrono::microseconds(5));
-        else
+        if (any_busy || !srv->queue.empty()) {
+            idle_since = Clock::now();
+            lock.unlock();
+            std::this_thread::yield();
+            lock.lock();
+        } else if (Clock::now() - idle_since < std::chrono::microseconds(500)) {
+            // stay awake briefly: a new request is likely soon
+            lock.unlock();
+            std::this_thread::yield();
+            lock.lock();
+        } else {
             srv->cv_work.wait(lock, [&] { return srv->stop || !srv->queue.empty(); });
+            idle_since = Clock::now();
+        }
     }
 }
 
@@ -200,6 +336,8 @@ PTRHASH_API int ptrhash_server_default_config(ptrhash_server_config *cfg) {
     cfg->max_batches = 1024;
     cfg->slot_keys = 1u << 22;
     cfg->max_queued_keys = 1ull << 28;
+    cfg->copy_threads = 4;
+    cfg->zero_copy = 1;
     return PTRHASH_OK;
 }
 
@@ -212,12 +350,17 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
         return ptrhash::set_error(PTRHASH_E_INVAL, "slot_keys must be 1..2^32");
     if (cfg->max_queued_keys < cfg->slot_keys)
         return ptrhash::set_error(PTRHASH_E_INVAL, "max_queued_keys must be >= slot_keys");
+    if (cfg->copy_threads < 0 || cfg->copy_threads > 64)
+        return ptrhash::set_error(PTRHASH_E_INVAL, "copy_threads must be 0..64");
     ptrhash_server *srv = new (std::nothrow) ptrhash_server();
     if (!srv) return ptrhash::set_error(PTRHASH_E_NOMEM, "server allocation failed");
     srv->cfg = *cfg;
     hipError_t e = hipGetDevice(&srv->device);
     int rc = e == hipSuccess ? PTRHASH_OK : hip_err(e, "hipGetDevice");
     srv->slots.resize(cfg->streams);
+    srv->grid = ptrhash::multi_grid();
+    const bool zc = cfg->zero_copy != 0;
+    const unsigned pin = zc ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
     for (Slot &s : srv->slots) {
         if (rc) break;
         const uint64_t kb = cfg->slot_keys * sizeof(uint64_t);
@@ -227,19 +370,32 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
             rc = hip_err(e, "stream/event creation");
             break;
         }
-        if (hipMalloc(&s.d_keys, kb) != hipSuccess || hipMalloc(&s.d_out, ob) != hipSuccess ||
-            hipHostMalloc(&s.h_keys, kb, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&s.h_out, ob, hipHostMallocDefault) != hipSuccess) {
-            rc = ptrhash::set_error(PTRHASH_E_NOMEM, "serving arena allocation failed");
+        if (hipHostMalloc(&s.h_keys, kb, pin) != hipSuccess || hipHostMalloc(&s.h_out, ob, pin) != hipSuccess) {
+            rc = ptrhash::set_error(PTRHASH_E_NOMEM, "serving staging allocation failed");
             break;
         }
-        rc = ptrhash_multi_plan_create(cfg->max_batches, &s.plan);
+        if (zc) {
+            if (hipHostMalloc(&s.h_table, ptrhash::multi_table_bytes(cfg->max_batches), pin) != hipSuccess ||
+                hipHostGetDevicePointer((void **)&s.v_table, s.h_table, 0) != hipSuccess ||
+                hipHostGetDevicePointer((void **)&s.v_keys, s.h_keys, 0) != hipSuccess ||
+                hipHostGetDevicePointer((void **)&s.v_out, s.h_out, 0) != hipSuccess) {
+                rc = ptrhash::set_error(PTRHASH_E_NOMEM, "mapped serving buffers failed");
+                break;
+            }
+        } else {
+            if (hipMalloc(&s.d_keys, kb) != hipSuccess || hipMalloc(&s.d_out, ob) != hipSuccess) {
+                rc = ptrhash::set_error(PTRHASH_E_NOMEM, "serving arena allocation failed");
+                break;
+            }
+            rc = ptrhash_multi_plan_create(cfg->max_batches, &s.plan);
+        }
     }
     if (rc) {
         for (Slot &s : srv->slots) free_slot(s);
         delete srv;
         return rc;
     }
+    srv->pool = new CopyPool(cfg->copy_threads);
     srv->worker = std::thread(run, srv);
     *out = srv;
     return PTRHASH_OK;
@@ -318,6 +474,11 @@ PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics
     st->p50_us = pct(0.50);
     st->p99_us = pct(0.99);
     st->max_us = v.empty() ? 0.0 : v.back();
+    std::vector<double> w(srv->waits);
+    std::sort(w.begin(), w.end());
+    auto wp = [&](double q) { return w.empty() ? 0.0 : w[std::min(w.size() - 1, (size_t)(q * (w.size() - 1) + 0.5))]; };
+    st->wait_p50_us = wp(0.50);
+    st->wait_p99_us = wp(0.99);
     return srv->error;
 }
 
@@ -325,6 +486,7 @@ PTRHASH_API int ptrhash_server_reset_stats(ptrhash_server *srv) {
     if (!srv) return ptrhash::set_error(PTRHASH_E_INVAL, "server is NULL");
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->latencies.clear();
+    srv->waits.clear();
     srv->completed = srv->launches = srv->keys_done = 0;
     return PTRHASH_OK;
 }
@@ -367,6 +529,7 @@ PTRHASH_API int ptrhash_server_destroy(ptrhash_server *srv) {
         free_slot(s);
     }
     const int err = srv->error;
+    delete srv->pool;
     delete srv;
     return err;
 }

@@ -20,6 +20,8 @@ GAMMA_CUBIC, GAMMA_LINEAR = 0, 1
 REMAP_CLEF, REMAP_U32, REMAP_NONE = 0, 1, 2
 KEY_U64, KEY_BYTES = 0, 1
 PRESET_DEFAULT, PRESET_FAST, PRESET_COMPACT = 0, 1, 2
+PRESET_SINGLE_MOD = 0x100
+REDUCE_POW2, REDUCE_MOD = 0, 1
 KERNEL_PLAIN, KERNEL_PIPELINED = 0, 1
 
 
@@ -41,10 +43,17 @@ class Params(C.Structure):
         ("remap_len", C.c_uint64),
         ("key_kind", C.c_uint32),
         ("index_bits", C.c_uint32),
+        ("reduce_kind", C.c_uint32),
+        ("pad_", C.c_uint32),
+        ("slots", C.c_uint64),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+    @property
+    def slots_per_part(self) -> int:
+        return self.slots if self.reduce_kind == REDUCE_MOD else 1 << self.log2_slots
 
     def copy(self) -> "Params":
         return Params.from_buffer_copy(self)
@@ -63,12 +72,13 @@ class QueryDesc(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("streams", C.c_int), ("max_batches", C.c_int), ("slot_keys", C.c_uint64),
-                ("max_queued_keys", C.c_uint64)]
+                ("max_queued_keys", C.c_uint64), ("copy_threads", C.c_int), ("zero_copy", C.c_int)]
 
 
 class ServerMetrics(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("launches", C.c_uint64), ("keys", C.c_uint64), ("queued", C.c_uint64),
-                ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double)]
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double),
+                ("wait_p50_us", C.c_double), ("wait_p99_us", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -100,6 +110,7 @@ _SIGS = {
     "ptrhash_query_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "ptrhash_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ptrhash_last_error": (C.c_char_p, []),
+    "ptrhash_set_occupancy": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "ptrhash_build_u64": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_int,
                                     C.POINTER(BuildInfo)]),
     "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
@@ -264,6 +275,12 @@ class Mphf:
     def set_kernel(self, kernel: int, keys_per_lane: int = 4, block: int = 256):
         _check(lib().ptrhash_set_kernel(self._h, int(kernel), int(keys_per_lane), int(block)), "ptrhash_set_kernel")
 
+    def set_occupancy(self, blocks_per_cu: int = 0) -> int:
+        """Cap resident workgroups per CU (0 = none); returns the effective cap."""
+        eff = C.c_int()
+        _check(lib().ptrhash_set_occupancy(self._h, int(blocks_per_cu), C.byref(eff)), "ptrhash_set_occupancy")
+        return eff.value
+
     def query_into(self, keys, out, stream=None):
         """keys: cuda uint64 tensor; out: cuda tensor of index_bits width."""
         n = keys.numel()
@@ -373,7 +390,8 @@ class Server:
     """Continuous-batching query server over resident MPHFs (host keys in,
     host indices out); see ptrhash_server_* in include/ptrhash.h."""
 
-    def __init__(self, streams=None, max_batches=None, slot_keys=None, max_queued_keys=None):
+    def __init__(self, streams=None, max_batches=None, slot_keys=None, max_queued_keys=None, copy_threads=None,
+                 zero_copy=None):
         cfg = ServerConfig()
         _check(lib().ptrhash_server_default_config(C.byref(cfg)), "ptrhash_server_default_config")
         if streams is not None:
@@ -382,6 +400,10 @@ class Server:
             cfg.max_batches = max_batches
         if slot_keys is not None:
             cfg.slot_keys = slot_keys
+        if copy_threads is not None:
+            cfg.copy_threads = copy_threads
+        if zero_copy is not None:
+            cfg.zero_copy = int(bool(zero_copy))
         if max_queued_keys is not None:
             cfg.max_queued_keys = max_queued_keys
         elif cfg.max_queued_keys < cfg.slot_keys:

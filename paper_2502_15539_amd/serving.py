@@ -57,7 +57,7 @@ def run_server(srv, reqs, arrivals):
     keys = sum(len(q) for _, q, _ in reqs)
     return {"requests": len(reqs), "keys": keys, "makespan_s": span, "req_per_s": len(reqs) / span,
             "keys_per_s": keys / span, "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-            "launches": st["launches"]}
+            "wait_p50_us": st["wait_p50_us"], "wait_p99_us": st["wait_p99_us"], "launches": st["launches"]}
 
 
 def run_plain_baseline(reqs, torch):
@@ -82,13 +82,36 @@ def run_plain_baseline(reqs, torch):
             "p99_us": float(np.percentile(lat, 99))}, outs
 
 
-def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), streams=2, threads=0, log=print):
+SERVER_CONFIGS = [  # (streams, slot_keys, copy_threads, zero_copy)
+    (2, 1 << 22, 4, 0), (4, 1 << 20, 8, 0), (8, 1 << 20, 8, 0),
+    (2, 1 << 22, 4, 1), (4, 1 << 20, 8, 1), (8, 1 << 20, 8, 1), (4, 1 << 18, 8, 1),
+]
+
+
+def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0, log=print):
     fleet = build_fleet(threads=threads, log=log)
     reqs = make_requests(fleet, n_requests)
-    srv = P.Server(streams=streams, max_batches=1024, slot_keys=1 << 22, max_queued_keys=1 << 31)
-    # warm up, then the saturated rate: everything queued at t = 0
+    # pick the server configuration by its saturated rate (everything queued at t = 0)
+    tried = {}
+    for streams, slot, copiers, zc in SERVER_CONFIGS:
+        srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
+                       copy_threads=copiers, zero_copy=zc)
+        run_server(srv, reqs[:500], np.zeros(500))
+        r = run_server(srv, reqs, np.zeros(len(reqs)))
+        # latency at a light open-loop load (25 % of this configuration's saturated rate)
+        light = run_server(srv, reqs[:5000], poisson_arrivals(5000, 0.25 * r["req_per_s"], seed=99))
+        r["light_p50_us"], r["light_p99_us"] = light["p50_us"], light["p99_us"]
+        tried[(streams, slot, copiers, zc)] = r
+        log(f"[serve] config streams={streams} slot={slot} copiers={copiers} zero_copy={zc}: "
+            f"{r['req_per_s']:.0f} req/s {r['keys_per_s'] / 1e9:.2f} G keys/s launches={r['launches']} "
+            f"light-load p50 {light['p50_us']:.0f}us p99 {light['p99_us']:.0f}us")
+        srv.close()
+    best = max(tried, key=lambda c: tried[c]["req_per_s"])
+    streams, slot, copiers, zc = best
+    sat = tried[best]
+    srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
+                   copy_threads=copiers, zero_copy=zc)
     run_server(srv, reqs[:500], np.zeros(500))
-    sat = run_server(srv, reqs, np.zeros(len(reqs)))
     log(f"[serve] saturated: {sat['req_per_s']:.0f} req/s, {sat['keys_per_s'] / 1e9:.2f} G keys/s")
     runs = []
     for i, f in enumerate(loads):
@@ -98,7 +121,8 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), streams=2,
         r["offered_fraction"] = f
         r["offered_req_per_s"] = rate
         runs.append(r)
-        log(f"[serve] load {f:.2f}: {r['req_per_s']:.0f} req/s p50 {r['p50_us']:.0f}us p99 {r['p99_us']:.0f}us")
+        log(f"[serve] load {f:.2f}: {r['req_per_s']:.0f} req/s p50 {r['p50_us']:.0f}us p99 {r['p99_us']:.0f}us "
+            f"(wait p50 {r['wait_p50_us']:.0f}us p99 {r['wait_p99_us']:.0f}us) launches={r['launches']}")
     srv.close()
     served = [o.copy() for _, _, o in reqs]
     base, base_out = run_plain_baseline(reqs[:2000], torch)
@@ -106,4 +130,10 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), streams=2,
     log(f"[serve] plain per-request baseline: {base['req_per_s']:.0f} req/s p50 {base['p50_us']:.0f}us "
         f"agree={agree}")
     return {"saturated": sat, "open_loop": runs, "plain_per_request": base, "served_equals_plain": agree,
-            "mphfs": len(fleet), "resident_keys": int(sum(len(k) for k, _ in fleet)), "streams": streams}
+            "mphfs": len(fleet), "resident_keys": int(sum(len(k) for k, _ in fleet)),
+            "server_config": {"streams": streams, "slot_keys": slot, "copy_threads": copiers, "zero_copy": zc,
+                              "max_batches": 1024},
+            "config_sweep": {f"streams={c[0]},slot={c[1]},copiers={c[2]},zero_copy={c[3]}":
+                             {"req_per_s": v["req_per_s"], "keys_per_s": v["keys_per_s"],
+                              "light_p50_us": v["light_p50_us"], "light_p99_us": v["light_p99_us"]}
+                             for c, v in tried.items()}}

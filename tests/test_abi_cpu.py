@@ -166,3 +166,20 @@ def test_builder_errors():
     with pytest.raises(P.PtrHashError) as e:
         P.build_u64(K.u64_keys(999), params=p)
     assert e.value.code == P.E_INVAL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 100, 5000, 77_777, 129_000])
+def test_single_mod_params_and_builder_match_oracle(n):
+    p = P.params_default(n, P.PRESET_DEFAULT | P.PRESET_SINGLE_MOD)
+    o = O.params_single_mod(n)
+    assert p.reduce_kind == P.REDUCE_MOD and p.num_parts == 1
+    assert (p.slots, p.buckets_per_part, p.remap_len) == (o.slots_per_part, o.buckets_per_part, o.remap_len)
+    keys = K.u64_keys(n, seed=17)
+    b = P.build_u64(keys, params=p)
+    m = O.build_u64(keys, params=o)
+    assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
+
+
+def test_single_mod_flag_keeps_multi_part_rule():
+    p = P.params_default(10**6, P.PRESET_DEFAULT | P.PRESET_SINGLE_MOD)
+    assert p.reduce_kind == P.REDUCE_POW2 and p.num_parts == 4

@@ -219,3 +219,44 @@ def test_device_string_generator_matches_host():
     hqd, hqo = K.string_query_stream(n, seed=7, order_seed=K.ORDER_SEED)
     assert np.array_equal(qo.cpu().numpy().view(np.uint64), hqo)
     assert np.array_equal(qd.cpu().numpy()[: int(hqo[-1])], hqd[: int(hqo[-1])])
+
+
+def test_occupancy_cap_and_autotuner(tmp_path, monkeypatch):
+    """Occupancy caps change only speed, never indices; the autotuner
+    applies its winner and answers the next call from its cache."""
+    from paper_2502_15539_amd import autotune
+
+    keys, m = oracle_mphf(65_537)
+    q = probe_keys(keys)
+    want = O.query_u64(m, q)
+    g = load(m, P.REMAP_CLEF, 32)
+    for occ in (1, 2, 4, 0):
+        g.set_kernel(P.KERNEL_PIPELINED, 4, 256)
+        eff = g.set_occupancy(occ)
+        say(f"[tune] occupancy {occ} -> {eff}")
+        assert np.array_equal(gpu_query(g, q, 32), want)
+    monkeypatch.setenv("PTRHASH_TUNE_CACHE", str(tmp_path / "tune.json"))
+    qt = torch.from_numpy(q.view(np.int64)).to(DEV)
+    out = torch.empty(len(q), dtype=torch.int32, device=DEV)
+    cands = autotune.candidates(kpls=(1, 4), blocks=(256,), occupancy=(0, 2))
+    best, res = autotune.tune(torch, g, lambda: g.query_into(qt, out), len(q), cands=cands, reps=1)
+    assert best in res and len(res) == len(cands)
+    best2, res2 = autotune.tune(torch, g, lambda: g.query_into(qt, out), len(q), cands=cands, reps=1)
+    assert best2 == best and res2 == {}
+    g.query_into(qt, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32).astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("n", [1, 3, 1000, 12_345, 100_000])
+def test_single_part_mod_reduce_parity(n):
+    keys = K.u64_keys(n, seed=55)
+    m = O.build_u64(keys, params=O.params_single_mod(n))
+    q = probe_keys(keys)
+    for remap in (P.REMAP_CLEF, P.REMAP_U32, P.REMAP_NONE):
+        want = O.query_u64(m, q, ORACLE_REMAP[remap])
+        g = load(m, remap, 32)
+        for kern, kpl, blk in VARIANTS[:1] + VARIANTS[4:6]:
+            say(f"[parity] single-part mod n={n} remap={remap} kernel={kern} kpl={kpl}")
+            g.set_kernel(kern, kpl, blk)
+            assert np.array_equal(gpu_query(g, q, 32), want)

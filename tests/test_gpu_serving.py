@@ -53,10 +53,11 @@ def requests(rng, count, max_size):
     return reqs
 
 
-def test_alone_equals_mix_equals_oracle():
+@pytest.mark.parametrize("zero_copy", [1, 0])
+def test_alone_equals_mix_equals_oracle(zero_copy):
     rng = np.random.default_rng(3)
     reqs = requests(rng, 120, 20_000)
-    srv = P.Server(streams=2, max_batches=64, slot_keys=1 << 16)
+    srv = P.Server(streams=2, max_batches=64, slot_keys=1 << 16, zero_copy=zero_copy)
     say(f"[serve] alone: {len(reqs)} requests")
     alone = []
     for g, q, out, want in reqs:
@@ -76,12 +77,13 @@ def test_alone_equals_mix_equals_oracle():
     srv.close()
 
 
-def test_replay_tiny_budget_no_loss():
+@pytest.mark.parametrize("zero_copy", [1, 0])
+def test_replay_tiny_budget_no_loss(zero_copy):
     """slot_keys of 3000 and 3 requests per launch force many launches and a
     long queue; every request is delivered once and correctly."""
     rng = np.random.default_rng(4)
     reqs = requests(rng, 400, 3000)
-    srv = P.Server(streams=2, max_batches=3, slot_keys=3000, max_queued_keys=1 << 30)
+    srv = P.Server(streams=2, max_batches=3, slot_keys=3000, max_queued_keys=1 << 30, zero_copy=zero_copy)
     arrivals = np.cumsum(rng.exponential(20.0, size=len(reqs)))
     say(f"[serve] replay {len(reqs)} requests, tiny budget")
     span = srv.replay([(g, q, out, t) for (g, q, out, _), t in zip(reqs, arrivals)])

@@ -239,3 +239,32 @@ def test_lambda4_linear_fails_full_cap():
     p, n = lambda4_params(O.GAMMA_LINEAR)
     with pytest.raises(O.BuildError):
         O.build_u64(K.u64_keys(n, seed=7), params=p, eviction_factor=10, max_attempts=1)
+
+
+def test_reduce_mod_definition():
+    rng = np.random.default_rng(8)
+    for S in (3, 5, 99, 10_102, 65_537, 1_000_003, (1 << 32) - 1):
+        for x in [0, 1, M64, S, S - 1] + [int(v) for v in rng.integers(0, 1 << 63, size=200, dtype=np.uint64) * 2 + 1]:
+            assert L.orc_reduce_mod(x, S) == x % S
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 100, 1000, 10_000, 77_777])
+def test_single_part_mod_bijection(n):
+    """Single part, S = ceil(n/alpha) not a power of two, reduce = x mod S
+    ("The reduce function", fast-mod variant): still a bijection, with a load
+    near alpha instead of down to one half."""
+    keys = K.u64_keys(n, seed=31)
+    p = O.params_single_mod(n)
+    S = p.slots_per_part
+    assert p.num_parts == 1 and S & (S - 1) != 0 and S >= n / 0.99 and S >= n + 16
+    assert S <= max(int(np.ceil(n / 0.99)), n + 16) + 1
+    m = O.build_u64(keys, params=p)
+    out = O.query_u64(m, keys)
+    assert is_perm(out, n)
+    assert np.array_equal(out, O.query_u64(m, keys, O.REMAP_PLAIN))
+    slots = O.query_u64(m, keys, O.REMAP_NONE)
+    assert slots.max() < S
+    h = [(C * int(k)) & M64 for k in keys[:50]]
+    for hh, s in zip(h, slots[:50]):
+        b = L.orc_bucket(p, hh)
+        assert s == (hh ^ ((C * (int(m.pilots[b]) ^ p.seed)) & M64)) % S
