@@ -133,8 +133,25 @@ def kernel_name(P, best):
     return f"pipelined(keys_per_lane={best[1]},block={best[2]}{occ})"
 
 
+def profiled_traffic(workload, ms, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, if the kernel sources still match the ones profiled."""
+    from paper_2502_15539_amd import profsum
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None, None
+    t = json.load(open(path))
+    if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
+        return None, {"stale_profile": path}
+    b = t["traffic_bytes_per_launch"]
+    return b, {"traffic_GBps": b / (ms / 1e3) / 1e9, "traffic_bytes_per_key": b / n,
+               "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": path}
+
+
 def record(args, n, ms, wall, desc, extra_config, dtype, per_key, **fields):
     achieved = per_key * n / (ms / 1e3) / 1e9
+    traffic, tinfo = profiled_traffic(args.workload, ms, n)
     rec = {
         "metric": METRIC,
         "value": n / (ms / 1e3),
@@ -151,7 +168,8 @@ def record(args, n, ms, wall, desc, extra_config, dtype, per_key, **fields):
         "config": {"workload": desc, "n": n, **extra_config, "parallelism": "single GPU"},
         "ns_per_key": ms * 1e6 / n,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_key": per_key},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_key": per_key,
+                     "traffic_info": tinfo},
         "timed_wall_s": wall,
     }
     rec.update(fields)

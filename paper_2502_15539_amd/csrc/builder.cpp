@@ -14,6 +14,9 @@
 // pure function of the keys and the parameters.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <queue>
@@ -87,18 +90,20 @@ enum PartStatus { kPartOk = 0, kPartFailed = 1 };
 struct PartWorker {
     const Geometry *geo = nullptr;
     std::vector<int32_t> owner;      // local slot -> local bucket
-    std::vector<uint32_t> stamp;     // local slot -> last trial that touched it
+    std::vector<uint64_t> taken;     // local slot bitmap (the paper's taken-slot bitvector)
+    std::vector<uint32_t> stamp;     // local slot -> last trial that touched it (large buckets)
     uint32_t cur = 0;
     std::vector<uint32_t> bstart;    // local bucket -> offset into bh
     std::vector<uint64_t> bh;        // hashes grouped by local bucket
     std::vector<int64_t> last;       // local bucket -> placement number
-    std::vector<uint32_t> slots;
+    std::vector<uint32_t> slots;     // slots of the bucket being placed
     uint64_t hp[256];
     uint64_t evictions = 0, max_bucket = 0;
 
     void init(const Geometry *g) {
         geo = g;
         owner.assign(g->S, kEmpty);
+        taken.assign((g->S + 63) / 64, 0);
         stamp.assign(g->S, 0);
         cur = 0;
         bstart.assign(g->B + 1, 0);
@@ -112,6 +117,38 @@ struct PartWorker {
             cur = 1;
         }
         return cur;
+    }
+
+    bool is_taken(uint32_t q) const { return (taken[q >> 6] >> (q & 63)) & 1u; }
+    void set_owner(uint32_t q, int32_t b) {
+        owner[q] = b;
+        if (b == kEmpty)
+            taken[q >> 6] &= ~(1ull << (q & 63));
+        else
+            taken[q >> 6] |= 1ull << (q & 63);
+    }
+
+    // Slots of a bucket's keys under pilot p; true if they are distinct
+    // (pairwise for small buckets, trial stamps for large ones).
+    static constexpr uint32_t kPairwise = 16;
+    bool distinct_slots(const uint64_t *kh, uint32_t s, uint32_t p, uint32_t *out) {
+        if (s <= kPairwise) {
+            for (uint32_t j = 0; j < s; ++j) {
+                const uint32_t q = slot(kh[j], p);
+                for (uint32_t i = 0; i < j; ++i)
+                    if (out[i] == q) return false;
+                out[j] = q;
+            }
+            return true;
+        }
+        const uint32_t st = next_stamp();
+        for (uint32_t j = 0; j < s; ++j) {
+            const uint32_t q = slot(kh[j], p);
+            if (stamp[q] == st) return false;
+            stamp[q] = st;
+            out[j] = q;
+        }
+        return true;
     }
 
     uint32_t slot(uint64_t h, uint32_t p) const {
@@ -144,6 +181,7 @@ struct PartWorker {
     PartStatus place(uint8_t *pilots /* this part's B pilots */, uint64_t max_evictions) {
         const uint32_t B = (uint32_t)geo->B;
         std::fill(owner.begin(), owner.end(), kEmpty);
+        std::fill(taken.begin(), taken.end(), 0ull);
         std::priority_queue<uint64_t> heap;  // (size << 32) | (~id): big first, then small id
         uint64_t maxs = 0;
         for (uint32_t b = 0; b < B; ++b) {
@@ -155,6 +193,7 @@ struct PartWorker {
         }
         max_bucket = std::max(max_bucket, maxs);
         slots.resize(std::max<uint64_t>(maxs, 1));
+        uint32_t *sl = slots.data();
         int64_t placed = 0;
         uint64_t ev = 0;
         auto size_of = [&](uint32_t b) { return (uint64_t)(bstart[b + 1] - bstart[b]); };
@@ -165,28 +204,26 @@ struct PartWorker {
             const uint32_t s = (uint32_t)size_of(b);
             int chosen = -1;
             // 1) smallest pilot with distinct, free slots
-            for (uint32_t p = 0; p < 256 && chosen < 0; ++p) {
-                const uint32_t st = next_stamp();
-                bool ok = true;
-                for (uint32_t j = 0; j < s; ++j) {
-                    const uint32_t q = slot(kh[j], p);
-                    if (owner[q] != kEmpty || stamp[q] == st) { ok = false; break; }
-                    stamp[q] = st;
+            if (s == 1) {
+                for (uint32_t p = 0; p < 256; ++p)
+                    if (!is_taken(slot(kh[0], p))) { chosen = (int)p; break; }
+            } else {
+                for (uint32_t p = 0; p < 256 && chosen < 0; ++p) {
+                    bool ok = true;
+                    for (uint32_t j = 0; j < s; ++j)
+                        if (is_taken(slot(kh[j], p))) { ok = false; break; }
+                    if (ok && distinct_slots(kh, s, p, sl)) chosen = (int)p;
                 }
-                if (ok) chosen = (int)p;
             }
             if (chosen < 0) {
                 // 2) least weighted collisions, never touching the recent ones
                 uint64_t best = UINT64_MAX;
                 for (uint32_t p = 0; p < 256; ++p) {
-                    const uint32_t st = next_stamp();
+                    if (!distinct_slots(kh, s, p, sl)) continue;
                     uint64_t cost = 0;
                     bool ok = true;
                     for (uint32_t j = 0; j < s; ++j) {
-                        const uint32_t q = slot(kh[j], p);
-                        if (stamp[q] == st) { ok = false; break; }
-                        stamp[q] = st;
-                        const int32_t o = owner[q];
+                        const int32_t o = owner[sl[j]];
                         if (o == kEmpty) continue;
                         if (last[o] + kRecent > placed) { ok = false; break; }
                         const uint64_t so = size_of((uint32_t)o);
@@ -200,12 +237,12 @@ struct PartWorker {
                     if (o == kEmpty) continue;
                     const uint64_t *oh = bh.data() + bstart[o];
                     const uint32_t os = (uint32_t)size_of((uint32_t)o);
-                    for (uint32_t t = 0; t < os; ++t) owner[slot(oh[t], pilots[o])] = kEmpty;
+                    for (uint32_t t = 0; t < os; ++t) set_owner(slot(oh[t], pilots[o]), kEmpty);
                     heap.push(((uint64_t)os << 32) | (0xffffffffu - (uint32_t)o));
                     ++ev;
                 }
             }
-            for (uint32_t j = 0; j < s; ++j) owner[slot(kh[j], (uint32_t)chosen)] = (int32_t)b;
+            for (uint32_t j = 0; j < s; ++j) set_owner(slot(kh[j], (uint32_t)chosen), (int32_t)b);
             pilots[b] = (uint8_t)chosen;
             last[b] = ++placed;
             if (ev > max_evictions) return kPartFailed;
@@ -370,6 +407,14 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     std::vector<uint64_t> h(n);
     Partitioned part;
     ptrhash_build_info local{};
+    const bool timing = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
+    auto tick = std::chrono::steady_clock::now();
+    auto phase = [&](const char *name) {
+        if (!timing) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[build] %-10s %8.3f s\n", name, std::chrono::duration<double>(now - tick).count());
+        tick = now;
+    };
     int rc = PTRHASH_E_BUILD;
     for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
         local.attempts = attempt + 1;
@@ -381,44 +426,18 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
                     h[i] = bytes ? hash_bytes(g.seed, src.data + src.offsets[i], src.offsets[i + 1] - src.offsets[i])
                                  : kMix * src.keys[i];
             });
+            phase("hash");
             partition(g, h.data(), n, bytes, threads, part);
+            phase("partition");
         }
         bool overflow = false;
         for (uint64_t p = 0; p < g.P; ++p) overflow |= part.start[p + 1] - part.start[p] > g.S;
         if (overflow && !bytes) return set_error(PTRHASH_E_BUILD, "a part holds more than S keys");
 
-        // duplicate / colliding hashes inside buckets
-        std::atomic<int> equal{0};  // 1 = hash collision of distinct keys, 2 = duplicate key
-        if (!overflow) {
-            std::vector<PartWorker> dw(threads);
-            parallel_for(threads, g.P, [&](int t, uint64_t p) {
-                if (dw[t].geo == nullptr) {
-                    dw[t].geo = &g;
-                    dw[t].bstart.assign(g.B + 1, 0);
-                }
-                const uint64_t s0 = part.start[p], cnt = part.start[p + 1] - s0;
-                dw[t].group(part.hashes.data() + s0, cnt);
-                if (!dw[t].has_equal_hashes()) return;
-                if (!bytes) { equal.store(2); return; }
-                // byte keys: compare the strings of equal hashes
-                std::vector<std::pair<uint64_t, uint64_t>> v(cnt);
-                for (uint64_t i = 0; i < cnt; ++i) v[i] = {part.hashes[s0 + i], part.ids[s0 + i]};
-                std::sort(v.begin(), v.end());
-                for (uint64_t i = 1; i < cnt; ++i) {
-                    if (v[i].first != v[i - 1].first) continue;
-                    const uint64_t a = v[i].second, b = v[i - 1].second;
-                    const uint64_t la = src.offsets[a + 1] - src.offsets[a], lb = src.offsets[b + 1] - src.offsets[b];
-                    if (la == lb && std::memcmp(src.data + src.offsets[a], src.data + src.offsets[b], la) == 0) {
-                        equal.store(2);
-                        return;
-                    }
-                    int expect = 0;
-                    equal.compare_exchange_strong(expect, 1);
-                }
-            });
-        }
-        if (equal.load() == 2) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
-        if (overflow || equal.load() == 1) continue;  // byte keys: reseed
+        // equal hashes inside a bucket (found while placing): 1 = distinct keys
+        // (byte keys: reseed), 2 = duplicate keys (error)
+        std::atomic<int> equal{0};
+        if (overflow) continue;  // byte keys: reseed
 
         std::vector<uint64_t> taken((g.P * g.S + 63) / 64, 0);
         std::atomic<bool> failed{false};
@@ -428,8 +447,30 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
             if (failed.load(std::memory_order_relaxed)) return;
             PartWorker &w = workers[t];
             if (w.geo == nullptr) w.init(&g);
-            const uint64_t s0 = part.start[p];
-            w.group(part.hashes.data() + s0, part.start[p + 1] - s0);
+            const uint64_t s0 = part.start[p], cnt = part.start[p + 1] - s0;
+            w.group(part.hashes.data() + s0, cnt);
+            if (w.has_equal_hashes()) {
+                int kind = 2;
+                if (bytes) {  // distinct strings with one hash only need a new seed
+                    kind = 1;
+                    std::vector<std::pair<uint64_t, uint64_t>> v(cnt);
+                    for (uint64_t i = 0; i < cnt; ++i) v[i] = {part.hashes[s0 + i], part.ids[s0 + i]};
+                    std::sort(v.begin(), v.end());
+                    for (uint64_t i = 1; i < cnt && kind == 1; ++i) {
+                        if (v[i].first != v[i - 1].first) continue;
+                        const uint64_t a = v[i].second, c = v[i - 1].second;
+                        const uint64_t la = src.offsets[a + 1] - src.offsets[a];
+                        const uint64_t lc = src.offsets[c + 1] - src.offsets[c];
+                        if (la == lc && std::memcmp(src.data + src.offsets[a], src.data + src.offsets[c], la) == 0)
+                            kind = 2;
+                    }
+                }
+                int prev = equal.load();
+                while (prev < kind && !equal.compare_exchange_weak(prev, kind)) {
+                }
+                failed.store(true);
+                return;
+            }
             w.max_bucket = 0;
             if (w.place(pilots + p * g.B, (uint64_t)kEvictionFactor * g.S) != kPartOk) {
                 failed.store(true);
@@ -444,6 +485,8 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
                     __atomic_fetch_or(&taken[q >> 6], 1ull << (q & 63), __ATOMIC_RELAXED);
                 }
         });
+        phase("place");
+        if (equal.load() == 2) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
         if (failed.load()) continue;
         local.evictions = 0;
         local.max_part_evictions = 0;
@@ -463,6 +506,7 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
             uint32_t *r = static_cast<uint32_t *>(remap);
             for (uint64_t i = 0; i < F.size(); ++i) r[i] = (uint32_t)F[i];
         }
+        phase("remap");
         params->seed = g.seed;
         if (info) *info = local;
         return PTRHASH_OK;

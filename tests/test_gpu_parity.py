@@ -136,7 +136,7 @@ def test_bytes_unaligned_and_edge_lengths():
     strs = [bytes([65 + (i * 7 + j) % 26 for j in range(L)]) for i, L in enumerate(list(range(41)) * 3)]
     strs = list(dict.fromkeys(strs))
     buf = b"".join(strs)
-    data = np.frombuffer(buf + b"\0" * 64, dtype=np.uint8)
+    data = np.frombuffer(buf + b"\0" * 64, dtype=np.uint8).copy()
     off = np.concatenate([[0], np.cumsum([len(s) for s in strs])]).astype(np.uint64)
     m = O.build_bytes(data, off)
     want = O.query_bytes(m, data, off)
