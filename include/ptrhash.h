@@ -304,6 +304,15 @@ typedef struct ptrhash_build_info {
 PTRHASH_API int ptrhash_build_u64(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                                   void *remap, int threads, ptrhash_build_info *info);
 
+/* As ptrhash_build_u64 with the keys in device memory: the hashes are
+ * computed and radix-sorted on the device (sorted hashes come grouped by part
+ * and bucket), copied to the host, and the pilot search runs on host threads.
+ * Same result as ptrhash_build_u64 on the same keys. Needs 16*n bytes of
+ * device memory plus the sort's scratch for the duration of the call; stream
+ * orders the device work and is synchronised before return. */
+PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
+                                         void *remap, int threads, ptrhash_build_info *info, hipStream_t stream);
+
 /* As ptrhash_build_u64 for byte strings data[offsets[i] .. offsets[i+1])
  * (host memory); equal 64-bit hashes of distinct strings cause a reseed. */
 PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,

@@ -23,6 +23,7 @@
 #include <thread>
 #include <vector>
 
+#include "builder.h"
 #include "errors.h"
 #include "ptrhash.h"
 
@@ -94,7 +95,8 @@ struct PartWorker {
     std::vector<uint32_t> stamp;     // local slot -> last trial that touched it (large buckets)
     uint32_t cur = 0;
     std::vector<uint32_t> bstart;    // local bucket -> offset into bh
-    std::vector<uint64_t> bh;        // hashes grouped by local bucket
+    std::vector<uint64_t> bh;        // hashes grouped by local bucket (when regrouped)
+    const uint64_t *bhp = nullptr;   // the part's hashes grouped by local bucket
     std::vector<int64_t> last;       // local bucket -> placement number
     std::vector<uint32_t> slots;     // slots of the bucket being placed
     uint64_t hp[256];
@@ -163,6 +165,16 @@ struct PartWorker {
         bh.resize(cnt);
         std::vector<uint32_t> fill(bstart.begin(), bstart.end() - 1);
         for (uint64_t i = 0; i < cnt; ++i) bh[fill[geo->local_bucket(h[i])]++] = h[i];
+        bhp = bh.data();
+    }
+
+    // Hashes sorted ascending are already grouped by bucket (the bucket index
+    // is non-decreasing in the hash); only the bucket offsets are needed.
+    void group_sorted(const uint64_t *h, uint64_t cnt) {
+        std::fill(bstart.begin(), bstart.end(), 0u);
+        for (uint64_t i = 0; i < cnt; ++i) bstart[geo->local_bucket(h[i]) + 1]++;
+        for (uint64_t b = 0; b < geo->B; ++b) bstart[b + 1] += bstart[b];
+        bhp = h;
     }
 
     // True if two keys of one bucket share a hash.
@@ -171,7 +183,7 @@ struct PartWorker {
         for (uint64_t b = 0; b < geo->B; ++b) {
             const uint32_t s = bstart[b + 1] - bstart[b];
             if (s < 2) continue;
-            tmp.assign(bh.begin() + bstart[b], bh.begin() + bstart[b + 1]);
+            tmp.assign(bhp + bstart[b], bhp + bstart[b + 1]);
             std::sort(tmp.begin(), tmp.end());
             if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end()) return true;
         }
@@ -200,7 +212,7 @@ struct PartWorker {
         while (!heap.empty()) {
             const uint32_t b = 0xffffffffu - (uint32_t)(heap.top() & 0xffffffffu);
             heap.pop();
-            const uint64_t *kh = bh.data() + bstart[b];
+            const uint64_t *kh = bhp + bstart[b];
             const uint32_t s = (uint32_t)size_of(b);
             int chosen = -1;
             // 1) smallest pilot with distinct, free slots
@@ -235,7 +247,7 @@ struct PartWorker {
                 for (uint32_t j = 0; j < s; ++j) {
                     const int32_t o = owner[slot(kh[j], (uint32_t)chosen)];
                     if (o == kEmpty) continue;
-                    const uint64_t *oh = bh.data() + bstart[o];
+                    const uint64_t *oh = bhp + bstart[o];
                     const uint32_t os = (uint32_t)size_of((uint32_t)o);
                     for (uint32_t t = 0; t < os; ++t) set_owner(slot(oh[t], pilots[o]), kEmpty);
                     heap.push(((uint64_t)os << 32) | (0xffffffffu - (uint32_t)o));
@@ -254,6 +266,7 @@ struct PartWorker {
 
 struct Partitioned {
     std::vector<uint64_t> hashes;   // grouped by part
+    bool sorted = false;            // hashes sorted ascending (grouped by bucket too)
     std::vector<uint64_t> ids;      // key ids in the same order (byte keys only)
     std::vector<uint64_t> start;    // part -> offset, P+1 entries
 };
@@ -376,9 +389,21 @@ int encode_clef(const std::vector<uint64_t> &F, uint8_t *out) {
 
 struct KeySource {
     const uint64_t *keys = nullptr;   // u64 keys, or
-    const uint8_t *data = nullptr;    // byte keys
+    const uint8_t *data = nullptr;    // byte keys, or
     const uint64_t *offsets = nullptr;
+    std::vector<uint64_t> *sorted = nullptr;  // hashes C*k of u64 keys, sorted ascending (consumed)
 };
+
+// Part boundaries of hashes sorted ascending: part p starts at the first hash
+// h with hi(P*h) >= p, i.e. h >= ceil(p*2^64/P).
+void sorted_part_starts(const Geometry &g, const std::vector<uint64_t> &h, std::vector<uint64_t> &start) {
+    start.assign(g.P + 1, 0);
+    for (uint64_t p = 1; p < g.P; ++p) {
+        const uint64_t first = (uint64_t)((((u128)p << 64) + g.P - 1) / g.P);
+        start[p] = (uint64_t)(std::lower_bound(h.begin(), h.end(), first) - h.begin());
+    }
+    start[g.P] = h.size();
+}
 
 int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
                int threads, ptrhash_build_info *info) {
@@ -386,6 +411,7 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     if (!params || !pilots) return set_error(PTRHASH_E_INVAL, "params/pilots is NULL");
     if (params->n != n || n == 0) return set_error(PTRHASH_E_INVAL, "params->n must equal n > 0");
     const bool bytes = src.data != nullptr;
+    if (src.sorted && bytes) return set_error(PTRHASH_E_INVAL, "sorted hashes are for u64 keys");
     if (params->key_kind != (bytes ? PTRHASH_KEY_BYTES : PTRHASH_KEY_U64))
         return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
     if (params->num_parts == 0 || params->num_parts > 0xffffffffull || params->buckets_per_part == 0 ||
@@ -404,7 +430,7 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     if (rbytes && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
     threads = pick_threads(threads);
 
-    std::vector<uint64_t> h(n);
+    std::vector<uint64_t> h(src.sorted ? 0 : n);
     Partitioned part;
     ptrhash_build_info local{};
     const bool timing = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
@@ -419,7 +445,15 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
         local.attempts = attempt + 1;
         g.seed = params->seed + attempt;
-        if (bytes || attempt == 0) {
+        if (src.sorted && attempt == 0) {
+            if (src.sorted->size() != n) return set_error(PTRHASH_E_INVAL, "sorted hash count != n");
+            part.hashes = std::move(*src.sorted);
+            part.sorted = true;
+            sorted_part_starts(g, part.hashes, part.start);
+            for (uint64_t i = 1; i < n; ++i)
+                if (part.hashes[i] == part.hashes[i - 1]) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
+            phase("partstarts");
+        } else if (!src.sorted && (bytes || attempt == 0)) {
             const uint64_t chunk = 1 << 16;
             parallel_for(threads, (n + chunk - 1) / chunk, [&](int, uint64_t c) {
                 for (uint64_t i = c * chunk, e = std::min(n, i + chunk); i < e; ++i)
@@ -448,7 +482,10 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
             PartWorker &w = workers[t];
             if (w.geo == nullptr) w.init(&g);
             const uint64_t s0 = part.start[p], cnt = part.start[p + 1] - s0;
-            w.group(part.hashes.data() + s0, cnt);
+            if (part.sorted)
+                w.group_sorted(part.hashes.data() + s0, cnt);
+            else
+                w.group(part.hashes.data() + s0, cnt);
             if (w.has_equal_hashes()) {
                 int kind = 2;
                 if (bytes) {  // distinct strings with one hash only need a new seed
@@ -516,6 +553,19 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
 }
 
 }  // namespace
+
+namespace ptrhash {
+int build_from_sorted(std::vector<uint64_t> &&sorted, uint64_t n, ptrhash_params *params, uint8_t *pilots,
+                      void *remap, int threads, ptrhash_build_info *info) {
+    KeySource src;
+    src.sorted = &sorted;
+    try {
+        return build_impl(src, n, params, pilots, remap, threads, info);
+    } catch (const std::bad_alloc &) {
+        return set_error(PTRHASH_E_NOMEM, "host allocation failed during construction");
+    }
+}
+}  // namespace ptrhash
 
 extern "C" {
 

@@ -113,6 +113,8 @@ _SIGS = {
     "ptrhash_set_occupancy": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "ptrhash_build_u64": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_int,
                                     C.POINTER(BuildInfo)]),
+    "ptrhash_build_u64_device": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                           C.c_int, C.POINTER(BuildInfo), C.c_void_p]),
     "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
@@ -216,6 +218,19 @@ def build_u64(keys: np.ndarray, params: Params | None = None, threads: int = 0, 
     info = BuildInfo()
     _check(lib().ptrhash_build_u64(_np_ptr(keys), len(keys), C.byref(p), _np_ptr(pilots), _np_ptr(remap),
                                    int(threads), C.byref(info)), "ptrhash_build_u64")
+    return Built(p, pilots, remap, info)
+
+
+def build_u64_device(keys, params: Params | None = None, threads: int = 0, stream=None, **kw) -> Built:
+    """Build from u64 keys in device memory (a cuda int64/uint64 tensor):
+    hashing and sorting on the device, pilot search on host threads."""
+    n = keys.numel()
+    p = (params if params is not None else params_default(n, **kw)).copy()
+    pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    remap = np.zeros(remap_bytes(p), dtype=np.uint8)
+    info = BuildInfo()
+    _check(lib().ptrhash_build_u64_device(_dev_ptr(keys), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
+                                          int(threads), C.byref(info), _stream(stream)), "ptrhash_build_u64_device")
     return Built(p, pilots, remap, info)
 
 
