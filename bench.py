@@ -194,13 +194,17 @@ def run_u64(args, torch, K, P):
     dev = "cuda"
     threads = args.threads or min(16, os.cpu_count() or 1)
     t0 = time.time()
-    keys = K.u64_keys(n)
+    # the key set is generated in HBM; construction hashes and sorts it on the
+    # device and runs the pilot search on host threads
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=dev), K.KEY_SEED)
+    torch.cuda.synchronize()
     t1 = time.time()
     preset = {"u64_1e9_fast": P.PRESET_FAST, "u64_1e9_compact": P.PRESET_COMPACT}.get(args.workload,
                                                                                       P.PRESET_DEFAULT)
-    built = P.build_u64(keys, index_bits=bits, threads=threads, preset=preset)
+    built = P.build_u64_device(keys, index_bits=bits, threads=threads, preset=preset)
     t2 = time.time()
     del keys
+    torch.cuda.empty_cache()
     if args.workload == "u64_1e9_phf":  # same pilots, queried without the remap
         built.params.remap_kind = P.REMAP_NONE
         built.remap = np.zeros(0, dtype=np.uint8)
@@ -221,10 +225,16 @@ def run_u64(args, torch, K, P):
     # roofline microbenchmarks on the same key stream
     table = torch.randint(0, 256, (p.num_parts * p.buckets_per_part,), dtype=torch.uint8, device=dev)
     gout = torch.empty(n, dtype=torch.int64, device=dev)
-    gcands = [(k, b) for k in (1, 2, 4, 8, 16) for b in (128, 256, 512)]
+    # tuned over the same knobs as the query (keys per lane, block, occupancy cap)
+    from paper_2502_15539_amd import autotune
+
+    gcands = [(k, b, o) for k in autotune.DEFAULT_KPL for b in autotune.DEFAULT_BLOCKS
+              for o in autotune.DEFAULT_OCCUPANCY]
     if args.gather != "auto":
-        gcands = [tuple(int(x) for x in args.gather.split(","))]
-    gsweep = {c: time_launches(torch, lambda: P.bench_gather(q, table, gout, c[0], c[1]), 3, 1) for c in gcands}
+        g = tuple(int(x) for x in args.gather.split(","))
+        gcands = [g if len(g) == 3 else g + (0,)]
+    gsweep = {c: time_launches(torch, lambda: P.bench_gather(q, table, gout, c[0], c[1], c[2]), 3, 1)
+              for c in gcands}
     gbest = min(gsweep, key=gsweep.get)
     gather_ms = gsweep[gbest]
     copy_ms = min(time_launches(torch, lambda: P.bench_copy(q, gout, k, 256), 3, 1) for k in (1, 4, 8))
@@ -260,7 +270,8 @@ def run_u64(args, torch, K, P):
                  "u64", per_key,
                  pct_gather_roofline=100.0 * gather_ms / ms,
                  gather_roofline={"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
-                                  "block": gbest[1], "table_bytes": p.num_parts * p.buckets_per_part},
+                                  "block": gbest[1], "blocks_per_cu": gbest[2],
+                                  "table_bytes": p.num_parts * p.buckets_per_part},
                  stream_copy_ms=copy_ms,
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  cpu_baseline=cpu,

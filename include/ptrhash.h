@@ -86,7 +86,8 @@ typedef struct ptrhash_params {
     uint32_t key_kind;    /* PTRHASH_KEY_* */
     uint32_t index_bits;  /* 32 or 64 */
     uint32_t reduce_kind; /* PTRHASH_REDUCE_* */
-    uint32_t pad_;
+    uint32_t hash_bits;   /* byte keys: 64 (0 means 64) or 128 -- the high half picks part and
+                             bucket, the low half the slot; u64 keys: 64 */
     uint64_t slots;       /* S when reduce_kind is PTRHASH_REDUCE_MOD */
 } ptrhash_params;
 
@@ -106,7 +107,8 @@ PTRHASH_API int ptrhash_destroy(ptrhash_handle *h);
  * shrinks S to the smallest power of two >= n/alpha. Presets: Default
  * (cubic, lambda 3.5, CacheLineEF), Fast (linear, lambda 3.0, u32 remap),
  * Compact (cubic, lambda 4.0, CacheLineEF), alpha = 0.99 for all.
- * index_bits 0 picks 32 when n <= 2^32, else 64.
+ * index_bits 0 picks 32 when n <= 2^32, else 64. Byte keys get 128-bit
+ * hashing when n > 2^32 (Section 3.1, "Hash functions"), else 64-bit.
  */
 PTRHASH_API int ptrhash_params_default(uint64_t n, int preset, uint32_t key_kind, uint32_t index_bits,
                                        uint64_t seed, ptrhash_params *out);
@@ -324,10 +326,11 @@ PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets
  * key in, one random byte from a table_len-byte table, stream a u64 out;
  * the memory pattern of a query without its arithmetic. copy: out[i] =
  * keys[i]. Both asynchronous on stream; keys_per_lane/block as in
- * ptrhash_set_kernel. */
+ * ptrhash_set_kernel; blocks_per_cu as in ptrhash_set_occupancy (0 = no cap),
+ * so the gather is tuned over the same knobs as the query. */
 PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const uint8_t *table,
                                      uint64_t table_len, uint64_t *out, int keys_per_lane, int block,
-                                     hipStream_t stream);
+                                     int blocks_per_cu, hipStream_t stream);
 /* pure gather: n random byte reads table[hi(mix(i) * table_len)] with no key
  * or index streams (mix = the SplitMix64 output mixer), spread over `lanes`
  * threads (a multiple of 256); sink receives one u32 sum per lane. */

@@ -53,6 +53,8 @@ typedef struct {
     int32_t gamma;             /* ORC_GAMMA_* */
     int32_t reduce_kind;       /* ORC_REDUCE_* */
     uint64_t remap_len;        /* P*S - n, entries of the remap table F */
+    int32_t hash_bits;         /* byte keys: 64, or 128 (high half -> part/bucket, low half -> slot) */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -87,6 +89,8 @@ int orc_params_for_single_mod(uint64_t n, double alpha, double lambda, int32_t g
 uint64_t orc_hash_u64(uint64_t key);
 uint64_t orc_fmix64(uint64_t k);
 uint64_t orc_hash_bytes(uint64_t seed, const uint8_t *s, uint64_t len);
+/* 128-bit byte-string hash: hi = H(seed), lo = H(seed ^ 0x9E3779B97F4A7C15). */
+void orc_hash_bytes128(uint64_t seed, const uint8_t *s, uint64_t len, uint64_t *hi, uint64_t *lo);
 
 uint64_t orc_part(const orc_params *p, uint64_t h);
 uint64_t orc_rel(const orc_params *p, uint64_t h);
@@ -96,6 +100,8 @@ uint64_t orc_hp(uint64_t seed, uint32_t pilot);
 uint64_t orc_reduce(uint64_t x, uint64_t S);
 uint64_t orc_reduce_mod(uint64_t x, uint64_t S);
 uint64_t orc_slot(const orc_params *p, uint64_t h, uint32_t pilot);
+/* slot with separate hashes for the part and for the reduce (128-bit keys) */
+uint64_t orc_slot2(const orc_params *p, uint64_t h_part, uint64_t h_slot, uint32_t pilot);
 
 /* Construction (Section 3.2). pilots: P*B bytes; F: remap_len u64 entries.
  * On success *p may carry a new seed (reseeded after failed attempts). */
@@ -115,6 +121,8 @@ uint32_t orc_select128(uint64_t lo, uint64_t hi, uint32_t r);
  * plain u64 F, or ignored for ORC_REMAP_NONE (non-minimal, returns slot). */
 uint64_t orc_query_hash(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,
                         const void *remap, uint64_t h);
+uint64_t orc_query_hash2(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,
+                         const void *remap, uint64_t h_bucket, uint64_t h_slot);
 int orc_query_u64(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,
                   const void *remap, const uint64_t *keys, uint64_t nq, uint64_t *out);
 int orc_query_bytes(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,

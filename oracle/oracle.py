@@ -44,10 +44,12 @@ class Params(C.Structure):
         ("gamma", C.c_int32),
         ("reduce_kind", C.c_int32),
         ("remap_len", C.c_uint64),
+        ("hash_bits", C.c_int32),
+        ("pad2_", C.c_int32),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}
 
 
 class BuildCfg(C.Structure):
@@ -85,6 +87,9 @@ def lib():
             "orc_hash_u64": (u64, [u64]),
             "orc_fmix64": (u64, [u64]),
             "orc_hash_bytes": (u64, [u64, C.c_void_p, u64]),
+            "orc_hash_bytes128": (None, [u64, C.c_void_p, u64, P(u64), P(u64)]),
+            "orc_slot2": (u64, [P(Params), u64, u64, C.c_uint32]),
+            "orc_query_hash2": (u64, [P(Params), C.c_void_p, C.c_int32, C.c_void_p, u64, u64]),
             "orc_part": (u64, [P(Params), u64]),
             "orc_rel": (u64, [P(Params), u64]),
             "orc_gamma": (u64, [C.c_int32, u64]),

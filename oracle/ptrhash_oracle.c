@@ -157,6 +157,18 @@ uint64_t orc_hash_bytes(uint64_t seed, const uint8_t *s, uint64_t len)
     return orc_fmix64(st);
 }
 
+/*
+ * reading: beyond 2^32 keys the paper switches to a 128-bit hash whose high
+ * 64 bits choose part and bucket and whose low 64 bits choose the slot
+ * ("Hash functions"). The 128-bit project hash is the 64-bit one twice, the
+ * second time with the seed xor-ed with 0x9E3779B97F4A7C15.
+ */
+void orc_hash_bytes128(uint64_t seed, const uint8_t *s, uint64_t len, uint64_t *hi, uint64_t *lo)
+{
+    *hi = orc_hash_bytes(seed, s, len);
+    *lo = orc_hash_bytes(seed ^ 0x9E3779B97F4A7C15ULL, s, len);
+}
+
 /* ---- Part and bucket (eq. partbucket; Section 3.3) ---- */
 
 /* part(k) = hi(P*h(k)) = floor(P*h/2^64). */
@@ -215,6 +227,11 @@ static uint64_t reduce_of(const orc_params *p, uint64_t x)
 uint64_t orc_slot(const orc_params *p, uint64_t h, uint32_t pilot)
 {
     return orc_part(p, h) * p->slots_per_part + reduce_of(p, h ^ orc_hp(p->seed, pilot));
+}
+
+uint64_t orc_slot2(const orc_params *p, uint64_t h_part, uint64_t h_slot, uint32_t pilot)
+{
+    return orc_part(p, h_part) * p->slots_per_part + reduce_of(p, h_slot ^ orc_hp(p->seed, pilot));
 }
 
 /* ---- CacheLineEF (Section 3.4, eq. clef) ---- */
@@ -306,8 +323,14 @@ uint64_t orc_clef_get(const uint8_t *clef, uint64_t i)
 uint64_t orc_query_hash(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,
                         const void *remap, uint64_t h)
 {
-    uint64_t b = orc_bucket(p, h);
-    uint64_t slot = orc_slot(p, h, pilots[b]);
+    return orc_query_hash2(p, pilots, remap_kind, remap, h, h);
+}
+
+uint64_t orc_query_hash2(const orc_params *p, const uint8_t *pilots, int32_t remap_kind,
+                         const void *remap, uint64_t h_bucket, uint64_t h_slot)
+{
+    uint64_t b = orc_bucket(p, h_bucket);
+    uint64_t slot = orc_slot2(p, h_bucket, h_slot, pilots[b]);
     if (remap_kind == ORC_REMAP_NONE || slot < p->n) return slot;
     if (remap_kind == ORC_REMAP_PLAIN) return ((const uint64_t *)remap)[slot - p->n];
     return orc_clef_get((const uint8_t *)remap, slot - p->n);
@@ -330,8 +353,14 @@ int orc_query_bytes(const orc_params *p, const uint8_t *pilots, int32_t remap_ki
     if (!p || !pilots || (nq && (!data || !offsets || !out))) return ORC_EINVAL;
     if (remap_kind != ORC_REMAP_NONE && p->remap_len && !remap) return ORC_EINVAL;
     for (uint64_t i = 0; i < nq; i++) {
-        uint64_t h = orc_hash_bytes(p->seed, data + offsets[i], offsets[i + 1] - offsets[i]);
-        out[i] = orc_query_hash(p, pilots, remap_kind, remap, h);
+        uint64_t hb, hs;
+        if (p->hash_bits == 128) {
+            orc_hash_bytes128(p->seed, data + offsets[i], offsets[i + 1] - offsets[i], &hb, &hs);
+        } else {
+            hb = orc_hash_bytes(p->seed, data + offsets[i], offsets[i + 1] - offsets[i]);
+            hs = hb;
+        }
+        out[i] = orc_query_hash2(p, pilots, remap_kind, remap, hb, hs);
     }
     return ORC_OK;
 }
@@ -390,7 +419,8 @@ static uint32_t heap_pop(heap_t *h)
 
 typedef struct {
     const orc_params *p;
-    const uint64_t *h;      /* key hashes */
+    const uint64_t *h;      /* key hashes (part and bucket) */
+    const uint64_t *hs;     /* key hashes for the slot (= h unless 128-bit) */
     const uint64_t *order;  /* key ids grouped by global bucket */
     const uint64_t *start;  /* global bucket -> first position in order */
     uint8_t *pilots;
@@ -408,7 +438,7 @@ static uint64_t bucket_slots(part_ctx *c, uint64_t part, uint32_t b, uint32_t pi
     uint64_t g = part * c->p->buckets_per_part + b;
     uint64_t s = c->start[g + 1] - c->start[g];
     for (uint64_t j = 0; j < s; j++)
-        slots[j] = reduce_of(c->p, c->h[c->order[c->start[g] + j]] ^ orc_hp(c->p->seed, pilot));
+        slots[j] = reduce_of(c->p, c->hs[c->order[c->start[g] + j]] ^ orc_hp(c->p->seed, pilot));
     return s;
 }
 
@@ -523,8 +553,9 @@ typedef int (*same_key_fn)(const void *ctx, uint64_t a, uint64_t b);
  * entry repeats its predecessor (reading: the entries before the first
  * defined one are 0).
  */
-static int build_attempt(const orc_params *p, const uint64_t *h, same_key_fn same, const void *sctx,
-                         uint8_t *pilots, uint64_t *F, orc_build_stats *st, uint64_t max_evictions)
+static int build_attempt(const orc_params *p, const uint64_t *h, const uint64_t *hs, same_key_fn same,
+                         const void *sctx, uint8_t *pilots, uint64_t *F, orc_build_stats *st,
+                         uint64_t max_evictions)
 {
     uint64_t n = p->n, P = p->num_parts, S = p->slots_per_part, B = p->buckets_per_part;
     uint64_t nb = P * B;
@@ -562,13 +593,14 @@ static int build_attempt(const orc_params *p, const uint64_t *h, same_key_fn sam
     for (uint64_t g = 0; g < nb; g++)
         for (uint64_t a = start[g]; a < start[g + 1]; a++)
             for (uint64_t b = a + 1; b < start[g + 1]; b++)
-                if (h[order[a]] == h[order[b]]) {
+                if (h[order[a]] == h[order[b]] && hs[order[a]] == hs[order[b]]) {
                     rc = same(sctx, order[a], order[b]) ? ORC_EDUPLICATE : ORC_EPART_FAIL;
                     goto out;
                 }
 
     c.p = p;
     c.h = h;
+    c.hs = hs;
     c.order = order;
     c.start = start;
     c.pilots = pilots;
@@ -660,7 +692,7 @@ int orc_build_u64(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
         orc_build_stats s1;
         memset(&s1, 0, sizeof s1);
         st->attempts = a + 1;
-        rc = build_attempt(p, h, same_u64, keys, pilots, F, &s1, factor * p->slots_per_part);
+        rc = build_attempt(p, h, h, same_u64, keys, pilots, F, &s1, factor * p->slots_per_part);
         st->placements += s1.placements;
         st->max_bucket_size = s1.max_bucket_size;
         if (rc != ORC_EPART_FAIL) {
@@ -686,16 +718,25 @@ int orc_build_bytes(orc_params *p, const uint8_t *data, const uint64_t *offsets,
     uint64_t factor, attempts;
     default_cfg(cfg, &factor, &attempts);
     uint64_t *h = malloc(p->n * sizeof *h);
-    if (!h) return ORC_ENOMEM;
+    uint64_t *hs = p->hash_bits == 128 ? malloc(p->n * sizeof *hs) : h;
+    if (!h || !hs) {
+        free(h);
+        if (hs != h) free(hs);
+        return ORC_ENOMEM;
+    }
     bytes_ctx bc = {data, offsets};
     int rc = ORC_EBUILD_FAILED;
     for (uint64_t a = 0; a < attempts; a++) {
-        for (uint64_t i = 0; i < p->n; i++)
-            h[i] = orc_hash_bytes(p->seed, data + offsets[i], offsets[i + 1] - offsets[i]);
+        for (uint64_t i = 0; i < p->n; i++) {
+            if (p->hash_bits == 128)
+                orc_hash_bytes128(p->seed, data + offsets[i], offsets[i + 1] - offsets[i], &h[i], &hs[i]);
+            else
+                h[i] = orc_hash_bytes(p->seed, data + offsets[i], offsets[i + 1] - offsets[i]);
+        }
         orc_build_stats s1;
         memset(&s1, 0, sizeof s1);
         st->attempts = a + 1;
-        rc = build_attempt(p, h, same_bytes, &bc, pilots, F, &s1, factor * p->slots_per_part);
+        rc = build_attempt(p, h, hs, same_bytes, &bc, pilots, F, &s1, factor * p->slots_per_part);
         st->placements += s1.placements;
         st->max_bucket_size = s1.max_bucket_size;
         if (rc != ORC_EPART_FAIL && rc != ORC_EPART_OVERFLOW) {
@@ -706,6 +747,7 @@ int orc_build_bytes(orc_params *p, const uint8_t *data, const uint64_t *offsets,
         rc = ORC_EBUILD_FAILED;
         p->seed++;
     }
+    if (hs != h) free(hs);
     free(h);
     return rc;
 }

@@ -18,8 +18,8 @@ import os
 from . import ptrhash as P
 
 DEFAULT_KPL = (1, 2, 4, 8, 16)
-DEFAULT_BLOCKS = (128, 256, 512)
-DEFAULT_OCCUPANCY = (0, 4, 2)  # 0 = uncapped
+DEFAULT_BLOCKS = (64, 128, 256, 512)
+DEFAULT_OCCUPANCY = (0, 2, 3, 4, 6, 8)  # resident workgroups per CU; 0 = uncapped
 
 
 def cache_path() -> str:

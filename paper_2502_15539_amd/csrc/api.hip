@@ -85,6 +85,7 @@ DevMphf device_view(const ptrhash_handle *h) {
     m.gamma = h->params.gamma;
     m.remap_kind = h->params.remap_kind;
     m.reduce_kind = h->params.reduce_kind;
+    m.hash128 = h->params.hash_bits == 128;
     if (h->params.reduce_kind == PTRHASH_REDUCE_MOD) {
         m.mod_slots = (uint32_t)h->params.slots;
         m.mod_magic = ~0ull / h->params.slots;  // = floor(2^64/S) since S is not a power of two
@@ -126,6 +127,10 @@ int check_params(const ptrhash_params *p) {
         return fail(PTRHASH_E_RANGE, "32-bit indices cannot hold values up to %llu", (unsigned long long)max_out);
     if (p->remap_kind == PTRHASH_REMAP_U32 && p->n > (1ull << 32))
         return fail(PTRHASH_E_RANGE, "u32 remap needs n <= 2^32");
+    if (p->hash_bits != 0 && p->hash_bits != 64 && p->hash_bits != 128)
+        return fail(PTRHASH_E_INVAL, "hash_bits must be 64 or 128");
+    if (p->hash_bits == 128 && p->key_kind != PTRHASH_KEY_BYTES)
+        return fail(PTRHASH_E_INVAL, "128-bit hashing is for byte keys");
     return PTRHASH_OK;
 }
 
@@ -241,6 +246,7 @@ PTRHASH_API int ptrhash_params_default(uint64_t n, int preset, uint32_t key_kind
     p.remap_len = P * S - n;
     p.key_kind = key_kind;
     p.index_bits = index_bits ? index_bits : (n <= (1ull << 32) ? 32u : 64u);
+    p.hash_bits = (key_kind == PTRHASH_KEY_BYTES && n > (1ull << 32)) ? 128u : 64u;
     if (single_mod && P == 1) {
         uint64_t Sm = (uint64_t)std::ceil((double)n / alpha);
         if (Sm < n + 16) Sm = n + 16;  // at least 16 free slots for tiny inputs
@@ -322,14 +328,13 @@ PTRHASH_API int ptrhash_set_kernel(ptrhash_handle *h, int kernel, int keys_per_l
     return PTRHASH_OK;
 }
 
-PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int *effective) {
-    if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
+// LDS bytes per workgroup that cap residency at blocks_per_cu workgroups per
+// CU (0 = no cap); *effective gets the cap the device's limits allow.
+static int occupancy_lds(int blocks_per_cu, uint32_t *lds, int *effective) {
     if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(PTRHASH_E_INVAL, "blocks_per_cu must be 0..64");
-    if (blocks_per_cu == 0) {
-        h->tuning.lds_bytes = 0;
-        if (effective) *effective = 0;
-        return PTRHASH_OK;
-    }
+    *lds = 0;
+    if (effective) *effective = 0;
+    if (blocks_per_cu == 0) return PTRHASH_OK;
     int dev = 0, per_cu = 0, per_block = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -338,8 +343,17 @@ PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int 
         return hip_fail(e, "device query");
     uint32_t bytes = (uint32_t)(per_cu / blocks_per_cu) & ~255u;
     if (bytes > (uint32_t)per_block) bytes = (uint32_t)per_block & ~255u;
-    h->tuning.lds_bytes = bytes;
+    *lds = bytes;
     if (effective) *effective = bytes ? per_cu / (int)bytes : 0;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int *effective) {
+    if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
+    uint32_t lds = 0;
+    const int rc = occupancy_lds(blocks_per_cu, &lds, effective);
+    if (rc) return rc;
+    h->tuning.lds_bytes = lds;
     return PTRHASH_OK;
 }
 
@@ -496,14 +510,18 @@ PTRHASH_API int ptrhash_query_multi(const ptrhash_query_desc *descs, int k, hipS
 }
 
 PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const uint8_t *table, uint64_t table_len,
-                                     uint64_t *out, int keys_per_lane, int block, hipStream_t stream) {
+                                     uint64_t *out, int keys_per_lane, int block, int blocks_per_cu,
+                                     hipStream_t stream) {
     if (!valid_tuning(kKernelPipelined, keys_per_lane, block)) return fail(PTRHASH_E_INVAL, "bad tuning");
     if (n_q == 0) return PTRHASH_OK;
     if (!keys || !table || !out || table_len == 0) return fail(PTRHASH_E_INVAL, "NULL or empty argument");
-    const Tuning t{kKernelPipelined, keys_per_lane, block};
-    const int rc = check_grid(n_q, t);
+    Tuning t{kKernelPipelined, keys_per_lane, block};
+    int rc = occupancy_lds(blocks_per_cu, &t.lds_bytes, nullptr);
     if (rc) return rc;
-    const hipError_t e = launch_bench_gather(keys, n_q, table, table_len, out, keys_per_lane, block, stream);
+    rc = check_grid(n_q, t);
+    if (rc) return rc;
+    const hipError_t e = launch_bench_gather(keys, n_q, table, table_len, out, keys_per_lane, block, t.lds_bytes,
+                                             stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "gather launch");
 }
 

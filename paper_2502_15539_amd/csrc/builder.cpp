@@ -35,6 +35,7 @@ constexpr int32_t kEmpty = -1;
 constexpr int kRecent = 16;
 constexpr int kEvictionFactor = 10;
 constexpr int kMaxSeeds = 16;
+constexpr uint64_t kWideSalt = 0x9E3779B97F4A7C15ull;  // seed of the low half of a 128-bit byte hash
 
 inline uint64_t mul_hi(uint64_t a, uint64_t b) { return (uint64_t)(((u128)a * b) >> 64); }
 inline uint64_t mul_lo(uint64_t a, uint64_t b) { return a * b; }
@@ -97,6 +98,8 @@ struct PartWorker {
     std::vector<uint32_t> bstart;    // local bucket -> offset into bh
     std::vector<uint64_t> bh;        // hashes grouped by local bucket (when regrouped)
     const uint64_t *bhp = nullptr;   // the part's hashes grouped by local bucket
+    std::vector<uint64_t> bs;        // slot hashes grouped alike (128-bit byte keys)
+    const uint64_t *bsp = nullptr;   // slot hashes grouped by local bucket (= bhp for 64-bit hashes)
     std::vector<int64_t> last;       // local bucket -> placement number
     std::vector<uint32_t> slots;     // slots of the bucket being placed
     uint64_t hp[256];
@@ -158,14 +161,25 @@ struct PartWorker {
     }
 
     // Group the part's hashes by local bucket (counting sort).
-    void group(const uint64_t *h, uint64_t cnt) {
+    void group(const uint64_t *h, const uint64_t *h2, uint64_t cnt) {
         std::fill(bstart.begin(), bstart.end(), 0u);
         for (uint64_t i = 0; i < cnt; ++i) bstart[geo->local_bucket(h[i]) + 1]++;
         for (uint64_t b = 0; b < geo->B; ++b) bstart[b + 1] += bstart[b];
         bh.resize(cnt);
         std::vector<uint32_t> fill(bstart.begin(), bstart.end() - 1);
+        if (h2) {
+            bs.resize(cnt);
+            for (uint64_t i = 0; i < cnt; ++i) {
+                const uint32_t d = fill[geo->local_bucket(h[i])]++;
+                bh[d] = h[i];
+                bs[d] = h2[i];
+            }
+            bhp = bh.data();
+            bsp = bs.data();
+            return;
+        }
         for (uint64_t i = 0; i < cnt; ++i) bh[fill[geo->local_bucket(h[i])]++] = h[i];
-        bhp = bh.data();
+        bhp = bsp = bh.data();
     }
 
     // Hashes sorted ascending are already grouped by bucket (the bucket index
@@ -174,16 +188,17 @@ struct PartWorker {
         std::fill(bstart.begin(), bstart.end(), 0u);
         for (uint64_t i = 0; i < cnt; ++i) bstart[geo->local_bucket(h[i]) + 1]++;
         for (uint64_t b = 0; b < geo->B; ++b) bstart[b + 1] += bstart[b];
-        bhp = h;
+        bhp = bsp = h;
     }
 
-    // True if two keys of one bucket share a hash.
+    // True if two keys of one bucket share their (bucket, slot) hashes.
     bool has_equal_hashes() {
-        std::vector<uint64_t> tmp;
+        std::vector<std::pair<uint64_t, uint64_t>> tmp;
         for (uint64_t b = 0; b < geo->B; ++b) {
             const uint32_t s = bstart[b + 1] - bstart[b];
             if (s < 2) continue;
-            tmp.assign(bhp + bstart[b], bhp + bstart[b + 1]);
+            tmp.clear();
+            for (uint32_t j = bstart[b]; j < bstart[b + 1]; ++j) tmp.emplace_back(bhp[j], bsp[j]);
             std::sort(tmp.begin(), tmp.end());
             if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end()) return true;
         }
@@ -212,7 +227,7 @@ struct PartWorker {
         while (!heap.empty()) {
             const uint32_t b = 0xffffffffu - (uint32_t)(heap.top() & 0xffffffffu);
             heap.pop();
-            const uint64_t *kh = bhp + bstart[b];
+            const uint64_t *kh = bsp + bstart[b];
             const uint32_t s = (uint32_t)size_of(b);
             int chosen = -1;
             // 1) smallest pilot with distinct, free slots
@@ -247,7 +262,7 @@ struct PartWorker {
                 for (uint32_t j = 0; j < s; ++j) {
                     const int32_t o = owner[slot(kh[j], (uint32_t)chosen)];
                     if (o == kEmpty) continue;
-                    const uint64_t *oh = bhp + bstart[o];
+                    const uint64_t *oh = bsp + bstart[o];
                     const uint32_t os = (uint32_t)size_of((uint32_t)o);
                     for (uint32_t t = 0; t < os; ++t) set_owner(slot(oh[t], pilots[o]), kEmpty);
                     heap.push(((uint64_t)os << 32) | (0xffffffffu - (uint32_t)o));
@@ -266,6 +281,7 @@ struct PartWorker {
 
 struct Partitioned {
     std::vector<uint64_t> hashes;   // grouped by part
+    std::vector<uint64_t> slot_hashes;  // 128-bit byte keys: low halves, same order
     bool sorted = false;            // hashes sorted ascending (grouped by bucket too)
     std::vector<uint64_t> ids;      // key ids in the same order (byte keys only)
     std::vector<uint64_t> start;    // part -> offset, P+1 entries
@@ -294,7 +310,8 @@ void parallel_for(int threads, uint64_t count, F &&fn) {
 }
 
 // Stable partition of hashes (and key ids) by part.
-void partition(const Geometry &g, const uint64_t *h, uint64_t n, bool keep_ids, int threads, Partitioned &out) {
+void partition(const Geometry &g, const uint64_t *h, const uint64_t *h2, uint64_t n, bool keep_ids, int threads,
+               Partitioned &out) {
     const uint64_t chunk = 1 << 20;
     const uint64_t nchunks = (n + chunk - 1) / chunk;
     std::vector<uint64_t> counts(nchunks * g.P, 0);
@@ -316,12 +333,14 @@ void partition(const Geometry &g, const uint64_t *h, uint64_t n, bool keep_ids, 
     out.start[g.P] = run;
     out.hashes.resize(n);
     if (keep_ids) out.ids.resize(n);
+    if (h2) out.slot_hashes.resize(n);
     parallel_for(threads, nchunks, [&](int, uint64_t c) {
         uint64_t *pos = counts.data() + c * g.P;
         for (uint64_t i = c * chunk, e = std::min(n, i + chunk); i < e; ++i) {
             const uint64_t d = pos[g.part(h[i])]++;
             out.hashes[d] = h[i];
             if (keep_ids) out.ids[d] = i;
+            if (h2) out.slot_hashes[d] = h2[i];
         }
     });
 }
@@ -416,7 +435,9 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
         return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
     if (params->num_parts == 0 || params->num_parts > 0xffffffffull || params->buckets_per_part == 0 ||
         params->log2_slots > 31 || params->gamma > PTRHASH_GAMMA_LINEAR || params->remap_kind > PTRHASH_REMAP_NONE ||
-        params->reduce_kind > PTRHASH_REDUCE_MOD)
+        params->reduce_kind > PTRHASH_REDUCE_MOD ||
+        (params->hash_bits != 0 && params->hash_bits != 64 && params->hash_bits != 128) ||
+        (params->hash_bits == 128 && params->key_kind != PTRHASH_KEY_BYTES))
         return set_error(PTRHASH_E_INVAL, "invalid params");
     const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
     if (mod && (params->num_parts != 1 || params->slots < 2 || params->slots >= (1ull << 31) ||
@@ -430,7 +451,8 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     if (rbytes && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
     threads = pick_threads(threads);
 
-    std::vector<uint64_t> h(src.sorted ? 0 : n);
+    const bool wide = bytes && params->hash_bits == 128;
+    std::vector<uint64_t> h(src.sorted ? 0 : n), h2(wide ? n : 0);
     Partitioned part;
     ptrhash_build_info local{};
     const bool timing = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
@@ -456,12 +478,19 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
         } else if (!src.sorted && (bytes || attempt == 0)) {
             const uint64_t chunk = 1 << 16;
             parallel_for(threads, (n + chunk - 1) / chunk, [&](int, uint64_t c) {
-                for (uint64_t i = c * chunk, e = std::min(n, i + chunk); i < e; ++i)
-                    h[i] = bytes ? hash_bytes(g.seed, src.data + src.offsets[i], src.offsets[i + 1] - src.offsets[i])
-                                 : kMix * src.keys[i];
+                for (uint64_t i = c * chunk, e = std::min(n, i + chunk); i < e; ++i) {
+                    if (!bytes) {
+                        h[i] = kMix * src.keys[i];
+                        continue;
+                    }
+                    const uint8_t *sp = src.data + src.offsets[i];
+                    const uint64_t len = src.offsets[i + 1] - src.offsets[i];
+                    h[i] = hash_bytes(g.seed, sp, len);
+                    if (wide) h2[i] = hash_bytes(g.seed ^ kWideSalt, sp, len);
+                }
             });
             phase("hash");
-            partition(g, h.data(), n, bytes, threads, part);
+            partition(g, h.data(), wide ? h2.data() : nullptr, n, bytes, threads, part);
             phase("partition");
         }
         bool overflow = false;
@@ -485,17 +514,22 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
             if (part.sorted)
                 w.group_sorted(part.hashes.data() + s0, cnt);
             else
-                w.group(part.hashes.data() + s0, cnt);
+                w.group(part.hashes.data() + s0, wide ? part.slot_hashes.data() + s0 : nullptr, cnt);
             if (w.has_equal_hashes()) {
                 int kind = 2;
                 if (bytes) {  // distinct strings with one hash only need a new seed
                     kind = 1;
-                    std::vector<std::pair<uint64_t, uint64_t>> v(cnt);
-                    for (uint64_t i = 0; i < cnt; ++i) v[i] = {part.hashes[s0 + i], part.ids[s0 + i]};
+                    struct E {
+                        uint64_t h, h2, id;
+                        bool operator<(const E &o) const { return h != o.h ? h < o.h : h2 != o.h2 ? h2 < o.h2 : id < o.id; }
+                    };
+                    std::vector<E> v(cnt);
+                    for (uint64_t i = 0; i < cnt; ++i)
+                        v[i] = {part.hashes[s0 + i], wide ? part.slot_hashes[s0 + i] : 0, part.ids[s0 + i]};
                     std::sort(v.begin(), v.end());
                     for (uint64_t i = 1; i < cnt && kind == 1; ++i) {
-                        if (v[i].first != v[i - 1].first) continue;
-                        const uint64_t a = v[i].second, c = v[i - 1].second;
+                        if (v[i].h != v[i - 1].h || v[i].h2 != v[i - 1].h2) continue;
+                        const uint64_t a = v[i].id, c = v[i - 1].id;
                         const uint64_t la = src.offsets[a + 1] - src.offsets[a];
                         const uint64_t lc = src.offsets[c + 1] - src.offsets[c];
                         if (la == lc && std::memcmp(src.data + src.offsets[a], src.data + src.offsets[c], la) == 0)

@@ -59,7 +59,7 @@ hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint6
                               void *out, bool out64, const Tuning &t, hipStream_t s);
 
 hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t table_len,
-                               uint64_t *out, int keys_per_lane, int block, hipStream_t s);
+                               uint64_t *out, int keys_per_lane, int block, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T, uint32_t *sink, uint32_t grid,
                                     hipStream_t s);
 hipError_t launch_bench_copy(const uint64_t *keys, uint64_t nq, uint64_t *out, int keys_per_lane, int block,

@@ -77,7 +77,7 @@ template <int K, typename OutT, bool Bytes>
 __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *__restrict__ keys,
                                              const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets,
                                              uint64_t nq, OutT *__restrict__ out, uint64_t base, uint32_t stride) {
-    uint64_t h[K];
+    uint64_t h[K], hs[K];  // hash for part/bucket, hash for the slot
     bool ok[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -86,12 +86,12 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
         if (Bytes) {
             if (ok[j]) {
                 const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
-                h[j] = hash_bytes(m.seed, data, o0, o1 - o0);
+                h[j] = hash_bytes(m.seed, data, o0, o1 - o0, m.hash128 != 0, hs[j]);
             } else {
-                h[j] = 0;
+                h[j] = hs[j] = 0;
             }
         } else {
-            h[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
+            h[j] = hs[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
         }
     }
     uint32_t part[K], pil[K];
@@ -102,7 +102,7 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
     }
     uint64_t v[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) v[j] = slot_of(m, h[j], part[j], pil[j]);
+    for (int j = 0; j < K; ++j) v[j] = slot_of(m, hs[j], part[j], pil[j]);
     finish_k<K>(m, v, ok);
 #pragma unroll
     for (int j = 0; j < K; ++j) {

@@ -33,7 +33,12 @@ struct DevMphf {
     uint32_t reduce_kind;
     uint32_t mod_slots;     // S for the mod reduce (one part)
     uint64_t mod_magic;     // floor(2^64 / S) for the mod reduce
+    uint32_t hash128;       // byte keys: 128-bit hash (high half: part/bucket, low half: slot)
+    uint32_t pad_;
 };
+
+// Seed of the low half of a 128-bit byte hash.
+constexpr uint64_t kWideSalt = 0x9E3779B97F4A7C15ull;
 
 // hi and lo 64-bit halves of a (32-bit) * b (64-bit): two 32x32->64
 // multiplies instead of a full 64x64 product.
@@ -164,8 +169,12 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
 // h = fmix64(st). data must be 8-byte aligned with readable bytes up to the
 // next 8-byte boundary after the string plus 8; words are read aligned and
 // funnel shifted.
-__device__ __forceinline__ uint64_t hash_bytes(uint64_t seed, const uint8_t *data, uint64_t o0, uint64_t len) {
+// With wide set, lo receives the same hash under seed ^ kWideSalt (the two
+// chains share the word loads).
+__device__ __forceinline__ uint64_t hash_bytes(uint64_t seed, const uint8_t *data, uint64_t o0, uint64_t len,
+                                               bool wide, uint64_t &lo) {
     uint64_t st = seed ^ (len * kMix);
+    uint64_t st2 = (seed ^ kWideSalt) ^ (len * kMix);
     const uint64_t *W = reinterpret_cast<const uint64_t *>(data + (o0 & ~7ull));
     const uint32_t sh = (uint32_t)(o0 & 7u) * 8u;
     uint64_t cur = W[0];
@@ -176,9 +185,12 @@ __device__ __forceinline__ uint64_t hash_bytes(uint64_t seed, const uint8_t *dat
         const uint64_t rem = len - 8 * w;
         if (rem < 8) word &= (1ull << (8 * rem)) - 1;
         st = fmix64(st ^ word);
+        if (wide) st2 = fmix64(st2 ^ word);
         cur = nxt;
     }
-    return fmix64(st);
+    const uint64_t hi = fmix64(st);
+    lo = wide ? fmix64(st2) : hi;
+    return hi;
 }
 
 }  // namespace ptrhash

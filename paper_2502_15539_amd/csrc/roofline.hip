@@ -85,14 +85,14 @@ hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T
 }
 
 hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t T, uint64_t *out,
-                               int K, int block, hipStream_t s) {
+                               int K, int block, uint32_t lds, hipStream_t s) {
     const dim3 grid((uint32_t)ceil_div(nq, (uint64_t)block * K)), blk((uint32_t)block);
     switch (K) {
-    case 1: hipLaunchKernelGGL(bench_gather_k<1>, grid, blk, 0, s, keys, nq, table, T, out); break;
-    case 2: hipLaunchKernelGGL(bench_gather_k<2>, grid, blk, 0, s, keys, nq, table, T, out); break;
-    case 4: hipLaunchKernelGGL(bench_gather_k<4>, grid, blk, 0, s, keys, nq, table, T, out); break;
-    case 8: hipLaunchKernelGGL(bench_gather_k<8>, grid, blk, 0, s, keys, nq, table, T, out); break;
-    case 16: hipLaunchKernelGGL(bench_gather_k<16>, grid, blk, 0, s, keys, nq, table, T, out); break;
+    case 1: hipLaunchKernelGGL(bench_gather_k<1>, grid, blk, lds, s, keys, nq, table, T, out); break;
+    case 2: hipLaunchKernelGGL(bench_gather_k<2>, grid, blk, lds, s, keys, nq, table, T, out); break;
+    case 4: hipLaunchKernelGGL(bench_gather_k<4>, grid, blk, lds, s, keys, nq, table, T, out); break;
+    case 8: hipLaunchKernelGGL(bench_gather_k<8>, grid, blk, lds, s, keys, nq, table, T, out); break;
+    case 16: hipLaunchKernelGGL(bench_gather_k<16>, grid, blk, lds, s, keys, nq, table, T, out); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -21,7 +21,7 @@ import re
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/kernels.hip", "csrc/mphf_device.h", "csrc/roofline.hip"]
+KERNEL_SOURCES = ["csrc/kernels.hip", "csrc/mphf_device.h"]
 
 
 def kernel_source_hash() -> str:

@@ -44,7 +44,7 @@ class Params(C.Structure):
         ("key_kind", C.c_uint32),
         ("index_bits", C.c_uint32),
         ("reduce_kind", C.c_uint32),
-        ("pad_", C.c_uint32),
+        ("hash_bits", C.c_uint32),
         ("slots", C.c_uint64),
     ]
 
@@ -118,7 +118,7 @@ _SIGS = {
     "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
-                                       C.c_void_p]),
+                                       C.c_int, C.c_void_p]),
     "ptrhash_bench_gather_pure": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
                                             C.c_void_p]),
     "ptrhash_bench_copy": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
@@ -323,9 +323,10 @@ class Mphf:
         return self.query_bytes_into(data, offsets, out, stream)
 
 
-def bench_gather(keys, table, out, keys_per_lane=4, block=256, stream=None):
+def bench_gather(keys, table, out, keys_per_lane=4, block=256, blocks_per_cu=0, stream=None):
     _check(lib().ptrhash_bench_gather(_dev_ptr(keys), keys.numel(), _dev_ptr(table), table.numel(), _dev_ptr(out),
-                                      int(keys_per_lane), int(block), _stream(stream)), "ptrhash_bench_gather")
+                                      int(keys_per_lane), int(block), int(blocks_per_cu), _stream(stream)),
+           "ptrhash_bench_gather")
 
 
 def bench_gather_pure(n, table, sink, stream=None):

@@ -45,7 +45,8 @@ def main():
     res = {"n": n, "copy_ms": min(t(lambda: P.bench_copy(keys, out, k, 256)) for k in (1, 2, 4)), "tables": []}
     for T in SIZES:
         table = torch.randint(0, 256, (T,), dtype=torch.uint8, device="cuda")
-        g = min(t(lambda: P.bench_gather(keys, table, out, k, b)) for k in (1, 4) for b in (256, 512))
+        g = min(t(lambda: P.bench_gather(keys, table, out, k, b, o)) for k in (1, 4) for b in (128, 512)
+                for o in (0, 4))
         pure = t(lambda: P.bench_gather_pure(n, table, sink))
         res["tables"].append({"table_bytes": T, "gather_ms": g, "gather_G_per_s": n / g / 1e6,
                               "pure_gather_ms": pure, "pure_G_per_s": n / pure / 1e6})

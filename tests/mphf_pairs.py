@@ -26,6 +26,7 @@ def lib_params(m: O.Mphf, remap_kind=P.REMAP_CLEF, index_bits=64, key_kind=P.KEY
     p.remap_len = o.remap_len
     p.key_kind = key_kind
     p.index_bits = index_bits
+    p.hash_bits = 128 if o.hash_bits == 128 else 64
     if o.reduce_kind == O.REDUCE_MOD:
         p.reduce_kind = P.REDUCE_MOD
         p.slots = o.slots_per_part

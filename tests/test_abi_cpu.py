@@ -183,3 +183,26 @@ def test_single_mod_params_and_builder_match_oracle(n):
 def test_single_mod_flag_keeps_multi_part_rule():
     p = P.params_default(10**6, P.PRESET_DEFAULT | P.PRESET_SINGLE_MOD)
     assert p.reduce_kind == P.REDUCE_POW2 and p.num_parts == 4
+
+
+def test_hash128_builder_equals_oracle():
+    data, off = K.strings(50_000, seed=19)
+    o = O.params_for(50_000)
+    o.hash_bits = 128
+    m = O.build_bytes(data, off, params=o)
+    p = P.params_default(50_000, key_kind=P.KEY_BYTES)
+    assert p.hash_bits == 64
+    p.hash_bits = 128
+    b = P.build_bytes(data, off, params=p)
+    assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
+
+
+def test_hash128_params_rule():
+    assert P.params_default(5 * 10**9, key_kind=P.KEY_BYTES).hash_bits == 128
+    assert P.params_default(10**9, key_kind=P.KEY_BYTES).hash_bits == 64
+    p = P.params_default(1000)
+    p.hash_bits = 128  # only byte keys take 128-bit hashing
+    m = P.Mphf()
+    with pytest.raises(P.PtrHashError) as e:
+        m.load(p, np.zeros(p.num_parts * p.buckets_per_part, np.uint8), np.zeros(P.remap_bytes(p), np.uint8))
+    assert e.value.code == P.E_INVAL

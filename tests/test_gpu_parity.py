@@ -260,3 +260,44 @@ def test_single_part_mod_reduce_parity(n):
             say(f"[parity] single-part mod n={n} remap={remap} kernel={kern} kpl={kpl}")
             g.set_kernel(kern, kpl, blk)
             assert np.array_equal(gpu_query(g, q, 32), want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 250_000, 2_000_000])
+def test_device_front_half_build_equals_oracle(n):
+    """Hash + radix sort on the device, pilot search on the host: the same
+    pilots and remap bytes as the oracle's construction."""
+    keys = K.u64_keys(n, seed=321)
+    say(f"[build-device] n={n}")
+    kt = torch.from_numpy(keys.view(np.int64)).to(DEV)
+    b = P.build_u64_device(kt, threads=8)
+    m = O.build_u64(keys)
+    assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
+    assert b.params.seed == m.params.seed
+
+
+def test_device_front_half_rejects_duplicates():
+    keys = K.u64_keys(5000, seed=3)
+    keys[4000] = keys[12]
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_u64_device(torch.from_numpy(keys.view(np.int64)).to(DEV))
+    assert e.value.code == P.E_DUPLICATE
+
+
+@pytest.mark.parametrize("n", [7, 30_000])
+def test_bytes_hash128_parity(n):
+    data, off = K.strings(n, seed=41)
+    o = O.params_for(n)
+    o.hash_bits = 128
+    m = O.build_bytes(data, off, params=o)
+    qd, qo = K.string_query_stream(n, seed=41)
+    want = O.query_bytes(m, qd, qo)
+    g = load(m, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES)
+    assert g.params.hash_bits == 128
+    dt = torch.from_numpy(qd).to(DEV)
+    ot = torch.from_numpy(qo.view(np.int64)).to(DEV)
+    for kern, kpl, blk in VARIANTS[:1] + VARIANTS[3:6]:
+        say(f"[parity-bytes128] n={n} kernel={kern} kpl={kpl}")
+        g.set_kernel(kern, kpl, blk)
+        got = g.query_bytes(dt, ot)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy().view(np.uint32).astype(np.uint64), want)

@@ -18,6 +18,12 @@ C = 0x517CC1B727220A95
 M64 = (1 << 64) - 1
 
 
+def C_u64():
+    import ctypes
+
+    return ctypes.c_uint64()
+
+
 def is_perm(out, n):
     return np.array_equal(np.sort(out), np.arange(n, dtype=np.uint64))
 
@@ -268,3 +274,42 @@ def test_single_part_mod_bijection(n):
     for hh, s in zip(h, slots[:50]):
         b = L.orc_bucket(p, hh)
         assert s == (hh ^ ((C * (int(m.pilots[b]) ^ p.seed)) & M64)) % S
+
+
+def wide_params(n, seed=0):
+    p = O.params_for(n, seed=seed)
+    p.hash_bits = 128
+    return p
+
+
+def test_hash128_is_two_seeded_hashes():
+    hi, lo = C_u64(), C_u64()
+    for s in (b"", b"abc", b"0123456789abcdefXYZ"):
+        buf = np.frombuffer(s + b"\0" * 8, dtype=np.uint8)
+        L.orc_hash_bytes128(7, buf.ctypes.data, len(s), hi, lo)
+        assert hi.value == O.hash_bytes(7, s)
+        assert lo.value == O.hash_bytes(7 ^ 0x9E3779B97F4A7C15, s)
+
+
+def test_hash128_split_roles():
+    """128-bit hashing: the high half alone decides part and bucket, the low
+    half alone the position inside the part ("Hash functions")."""
+    p = wide_params(1_000_000)
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        hb, hs1, hs2 = (int(x) for x in rng.integers(0, 1 << 63, size=3, dtype=np.uint64))
+        part = L.orc_part(p, hb)
+        s1 = L.orc_slot2(p, hb, hs1, 9)
+        s2 = L.orc_slot2(p, hb, hs2, 9)
+        S = p.slots_per_part
+        assert s1 // S == part and s2 // S == part
+        assert s1 % S == L.orc_reduce(hs1 ^ L.orc_hp(p.seed, 9), S)
+
+
+def test_hash128_strings_bijection():
+    data, off = K.strings(40_000, seed=12)
+    m = O.build_bytes(data, off, params=wide_params(40_000))
+    out = O.query_bytes(m, data, off)
+    assert is_perm(out, 40_000)
+    m64 = O.build_bytes(data, off)
+    assert not np.array_equal(out, O.query_bytes(m64, data, off))
