@@ -62,8 +62,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="u64_1e9", choices=sorted(WORKLOADS))
-    ap.add_argument("--kernel", default="auto", help="auto | plain | K,BLOCK (pipelined)")
-    ap.add_argument("--gather", default="auto", help="auto | K,BLOCK for the gather roofline kernel")
+    ap.add_argument("--kernel", default="auto",
+                    help="auto | plain | K,BLOCK[,BLOCKS_PER_CU] (pipelined; occupancy cap 0 = none)")
+    ap.add_argument("--gather", default="auto", help="auto | K,BLOCK[,BLOCKS_PER_CU] for the gather roofline")
     ap.add_argument("--cpu-sample", type=int, default=200_000_000, help="oracle sample size (keys); 0 = skip")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the build (0 = all, max 16)")
     ap.add_argument("--requests", type=int, default=20000, help="serving workload: requests per run")
@@ -90,8 +91,8 @@ def kernel_candidates(P, spec, bytes_keys=False):
     if spec == "plain":
         return [(P.KERNEL_PLAIN, 1, 256, 0)]
     if spec != "auto":
-        kk, bb = (int(x) for x in spec.split(","))
-        return [(P.KERNEL_PIPELINED, kk, bb, 0)]
+        v = [int(x) for x in spec.split(",")]
+        return [(P.KERNEL_PIPELINED, v[0], v[1], v[2] if len(v) > 2 else 0)]
     return autotune.candidates(kpls=(1, 2, 4, 8) if bytes_keys else (1, 2, 4, 8, 16))
 
 
