@@ -93,7 +93,7 @@ def kernel_candidates(P, spec, bytes_keys=False):
     if spec != "auto":
         v = [int(x) for x in spec.split(",")]
         return [(P.KERNEL_PIPELINED, v[0], v[1], v[2] if len(v) > 2 else 0)]
-    return autotune.candidates(kpls=(1, 2, 4, 8) if bytes_keys else (1, 2, 4, 8, 16))
+    return autotune.candidates_for(P.KEY_BYTES if bytes_keys else P.KEY_U64)
 
 
 def tune_and_time(torch, P, mphf, run, args, n_q, bytes_keys=False):
@@ -245,7 +245,7 @@ def run_u64(args, torch, K, P):
         built.params.remap_kind = P.REMAP_NONE
         built.remap = np.zeros(0, dtype=np.uint8)
     p = built.params
-    log(f"[bench] keygen {t1 - t0:.1f}s build {t2 - t1:.1f}s  P={p.num_parts} S=2^{p.log2_slots} "
+    log(f"[bench] keygen {t1 - t0:.1f}s build {t2 - t1:.1f}s ({built.placement} search)  P={p.num_parts} S=2^{p.log2_slots} "
         f"B={p.buckets_per_part} bits/key={built.bits_per_key:.3f} evictions={built.info.evictions}")
     mphf = P.Mphf.from_built(built)
 
@@ -297,7 +297,7 @@ def run_u64(args, torch, K, P):
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  cpu_baseline=cpu,
                  parity={"bijective_members": bij, "remap_fraction": rfrac},
-                 build_s=t2 - t1,
+                 build_s=t2 - t1, build_search=built.placement,
                  paper_cpu_context_ns_per_key={"loop": 12, "stream": 8, "default_clef_loop": 21.0,
                                                "default_clef_stream": 8.7})
     if args.workload != "u64_1e9":

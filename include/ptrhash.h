@@ -315,6 +315,24 @@ PTRHASH_API int ptrhash_build_u64(const uint64_t *keys, uint64_t n, ptrhash_para
 PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                                          void *remap, int threads, ptrhash_build_info *info, hipStream_t stream);
 
+/* As ptrhash_build_u64 with the keys in device memory and the whole pilot
+ * search on the device too (Section 3.2 "Construction"): the hashes are
+ * radix-sorted, bucket boundaries and a per-part (size descending, bucket
+ * id) order are built on the device, and one wavefront per part runs the
+ * hash-evict search with the part's taken-slot bitvector in LDS. The result
+ * is the same as ptrhash_build_u64 on the same keys, byte for byte; only the
+ * remap table is assembled on the host from the taken-slot bitvector.
+ * Limits: the S bits of a part must fit one workgroup's LDS (S <= 2^20 on
+ * gfx950), S a multiple of 32 when P > 1, buckets of at most 2048 keys;
+ * outside them the call returns E_RANGE and ptrhash_build_u64_device
+ * (host search) applies. Device memory: about 16*n + 33*P*B + P*S/8 bytes
+ * plus 16*S bytes per compute unit, for the duration of the call. stream
+ * orders the device work and is synchronised before return. Errors: E_INVAL,
+ * E_DUPLICATE, E_BUILD (a part with more than S keys, or 16 failed seeds),
+ * E_RANGE, E_NOMEM, E_HIP. */
+PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
+                                      void *remap, ptrhash_build_info *info, hipStream_t stream);
+
 /* As ptrhash_build_u64 for byte strings data[offsets[i] .. offsets[i+1])
  * (host memory); equal 64-bit hashes of distinct strings cause a reseed. */
 PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,

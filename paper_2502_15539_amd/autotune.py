@@ -20,6 +20,7 @@ from . import ptrhash as P
 DEFAULT_KPL = (1, 2, 4, 8, 16)
 DEFAULT_BLOCKS = (64, 128, 256, 512)
 DEFAULT_OCCUPANCY = (0, 2, 3, 4, 6, 8)  # resident workgroups per CU; 0 = uncapped
+BYTES_KPL = (1, 2, 4, 8)  # string keys hold more registers per key in flight
 
 
 def cache_path() -> str:
@@ -42,6 +43,11 @@ def candidates(kpls=DEFAULT_KPL, blocks=DEFAULT_BLOCKS, occupancy=DEFAULT_OCCUPA
             for o in occupancy:
                 out.append((P.KERNEL_PIPELINED, k, b, o))
     return out
+
+
+def candidates_for(key_kind):
+    """The sweep used for a key kind (u64 or byte strings)."""
+    return candidates(kpls=BYTES_KPL if key_kind == P.KEY_BYTES else DEFAULT_KPL)
 
 
 def _time(torch, fn, reps, warmup=1):

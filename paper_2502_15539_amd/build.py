@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -13,7 +14,8 @@ LIB = os.path.join(HERE, "libptrhash_hip.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PTRHASH_ARCH", "gfx950")
 
-HIP_SOURCES = ["api.hip", "kernels.hip", "roofline.hip", "keygen.hip", "server.hip", "build_device.hip"]
+HIP_SOURCES = ["api.hip", "kernels.hip", "roofline.hip", "keygen.hip", "server.hip", "build_device.hip",
+               "place_device.hip"]
 CXX_SOURCES = ["builder.cpp"]
 
 # Packed FP32 instructions are kept out of every HIP object on purpose.
@@ -37,15 +39,14 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     """Compile every source (always, even if a library exists) and link."""
     os.makedirs(OBJDIR, exist_ok=True)
-    objs = []
-    for src in HIP_SOURCES:
-        obj = os.path.join(OBJDIR, src + ".o")
-        _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    for src in CXX_SOURCES:
-        obj = os.path.join(OBJDIR, src + ".o")
-        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    jobs = [(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(OBJDIR, src + ".o")],
+             os.path.join(OBJDIR, src + ".o")) for src in HIP_SOURCES]
+    jobs += [(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(OBJDIR, src + ".o")],
+              os.path.join(OBJDIR, src + ".o")) for src in CXX_SOURCES]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1), 8))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)

@@ -424,15 +424,10 @@ void sorted_part_starts(const Geometry &g, const std::vector<uint64_t> &h, std::
     start[g.P] = h.size();
 }
 
-int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
-               int threads, ptrhash_build_info *info) {
+// Parameter checks shared by every construction path (params->n is already
+// known to equal the key count).
+int check_geometry(const ptrhash_params *params) {
     using ptrhash::set_error;
-    if (!params || !pilots) return set_error(PTRHASH_E_INVAL, "params/pilots is NULL");
-    if (params->n != n || n == 0) return set_error(PTRHASH_E_INVAL, "params->n must equal n > 0");
-    const bool bytes = src.data != nullptr;
-    if (src.sorted && bytes) return set_error(PTRHASH_E_INVAL, "sorted hashes are for u64 keys");
-    if (params->key_kind != (bytes ? PTRHASH_KEY_BYTES : PTRHASH_KEY_U64))
-        return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
     if (params->num_parts == 0 || params->num_parts > 0xffffffffull || params->buckets_per_part == 0 ||
         params->log2_slots > 31 || params->gamma > PTRHASH_GAMMA_LINEAR || params->remap_kind > PTRHASH_REMAP_NONE ||
         params->reduce_kind > PTRHASH_REDUCE_MOD ||
@@ -443,10 +438,39 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
     if (mod && (params->num_parts != 1 || params->slots < 2 || params->slots >= (1ull << 31) ||
                 (params->slots & (params->slots - 1)) == 0))
         return set_error(PTRHASH_E_INVAL, "mod reduce: one part, 2 <= S < 2^31, S not a power of two");
+    const uint64_t S = mod ? params->slots : 1ull << params->log2_slots;
+    if (params->num_parts * S < params->n || params->remap_len != params->num_parts * S - params->n)
+        return set_error(PTRHASH_E_INVAL, "P*S/remap_len");
+    if (params->buckets_per_part >= (1ull << 31)) return set_error(PTRHASH_E_RANGE, "too many buckets per part");
+    return PTRHASH_OK;
+}
+
+// F from the taken-slot bitvector, then its encoding into remap.
+int write_remap(const Geometry &g, const ptrhash_params *params, const std::vector<uint64_t> &taken, void *remap) {
+    std::vector<uint64_t> F;
+    int rc = build_remap(g, taken, F);
+    if (rc) return rc;
+    if (params->remap_kind == PTRHASH_REMAP_CLEF) return encode_clef(F, static_cast<uint8_t *>(remap));
+    if (params->remap_kind == PTRHASH_REMAP_U32) {
+        uint32_t *r = static_cast<uint32_t *>(remap);
+        for (uint64_t i = 0; i < F.size(); ++i) r[i] = (uint32_t)F[i];
+    }
+    return PTRHASH_OK;
+}
+
+int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
+               int threads, ptrhash_build_info *info) {
+    using ptrhash::set_error;
+    if (!params || !pilots) return set_error(PTRHASH_E_INVAL, "params/pilots is NULL");
+    if (params->n != n || n == 0) return set_error(PTRHASH_E_INVAL, "params->n must equal n > 0");
+    const bool bytes = src.data != nullptr;
+    if (src.sorted && bytes) return set_error(PTRHASH_E_INVAL, "sorted hashes are for u64 keys");
+    if (params->key_kind != (bytes ? PTRHASH_KEY_BYTES : PTRHASH_KEY_U64))
+        return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
+    if (int rc = check_geometry(params)) return rc;
+    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
     Geometry g{n, params->num_parts, mod ? params->slots : 1ull << params->log2_slots, params->buckets_per_part,
                params->seed, params->log2_slots, params->gamma, mod};
-    if (g.P * g.S < n || params->remap_len != g.P * g.S - n) return set_error(PTRHASH_E_INVAL, "P*S/remap_len");
-    if (g.B >= (1ull << 31)) return set_error(PTRHASH_E_RANGE, "too many buckets per part");
     const uint64_t rbytes = ptrhash_remap_bytes(params);
     if (rbytes && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
     threads = pick_threads(threads);
@@ -567,16 +591,8 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
             local.max_part_evictions = std::max(local.max_part_evictions, part_ev[p]);
             local.max_bucket_size = std::max(local.max_bucket_size, part_max[p]);
         }
-        std::vector<uint64_t> F;
-        rc = build_remap(g, taken, F);
+        rc = write_remap(g, params, taken, remap);
         if (rc) return rc;
-        if (params->remap_kind == PTRHASH_REMAP_CLEF) {
-            rc = encode_clef(F, static_cast<uint8_t *>(remap));
-            if (rc) return rc;
-        } else if (params->remap_kind == PTRHASH_REMAP_U32) {
-            uint32_t *r = static_cast<uint32_t *>(remap);
-            for (uint64_t i = 0; i < F.size(); ++i) r[i] = (uint32_t)F[i];
-        }
         phase("remap");
         params->seed = g.seed;
         if (info) *info = local;
@@ -589,6 +605,25 @@ int build_impl(const KeySource &src, uint64_t n, ptrhash_params *params, uint8_t
 }  // namespace
 
 namespace ptrhash {
+int check_build_params(uint64_t n, const ptrhash_params *params, uint32_t key_kind) {
+    if (!params) return set_error(PTRHASH_E_INVAL, "params is NULL");
+    if (params->n != n || n == 0) return set_error(PTRHASH_E_INVAL, "params->n must equal n > 0");
+    if (params->key_kind != key_kind) return set_error(PTRHASH_E_INVAL, "params->key_kind does not match the keys");
+    return check_geometry(params);
+}
+
+int remap_from_taken(const ptrhash_params *params, const std::vector<uint64_t> &taken, void *remap) {
+    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
+    Geometry g{params->n, params->num_parts, mod ? params->slots : 1ull << params->log2_slots,
+               params->buckets_per_part, params->seed, params->log2_slots, params->gamma, mod};
+    if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
+    try {
+        return write_remap(g, params, taken, remap);
+    } catch (const std::bad_alloc &) {
+        return set_error(PTRHASH_E_NOMEM, "host allocation failed building the remap");
+    }
+}
+
 int build_from_sorted(std::vector<uint64_t> &&sorted, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                       void *remap, int threads, ptrhash_build_info *info) {
     KeySource src;

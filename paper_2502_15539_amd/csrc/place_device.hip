@@ -1,0 +1,815 @@
+// Pilot search on the device (Section 3.2 "Construction"; the hash-evict
+// search of Section 3.2 "Hash-evict", the 10*S eviction limit of Section 4).
+//
+// Parts are independent, so each part is searched by one wavefront that owns
+// the part's taken-slot bitvector in LDS (S bits; 128 KiB at S = 2^20). The
+// rules are exactly those of the host builder, so the device reaches the same
+// pilots: buckets in order of (size descending, bucket id ascending); the
+// smallest pilot in [0, 256) whose slots are free and pairwise distinct;
+// otherwise, among pilots with distinct slots that touch none of the 16 most
+// recently placed buckets, the one with the least sum over colliding keys of
+// (size of the owning bucket)^2, smallest pilot first on ties; its owners are
+// evicted and requeued. Requeued buckets wait in a small max-heap in LDS;
+// merging it with the pre-sorted bucket order pops buckets in the same order
+// as one priority queue holding both.
+//
+// Inputs come from device passes over the sorted hashes (the part and the
+// bucket of a key are non-decreasing in its hash): bucket start offsets, the
+// per-part (size desc, id asc) order from a radix sort, and a copy of the
+// hashes laid out in that order so the search streams them.
+#include <hipcub/hipcub.hpp>
+
+#include "internal.h"
+#include "place_device.h"
+
+namespace ptrhash {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRecent = 16;
+constexpr uint32_t kHeapCap = 1024;       // requeued buckets waiting at once
+constexpr int kMaxRegs = 32;              // bucket keys held per lane: sizes up to 64 * 32
+constexpr uint32_t kMaxBucket = kWave * kMaxRegs;
+
+// Slot record written when a bucket is placed: owner bucket (local id), its
+// placement number, its size and its pilot.
+struct SlotRec {
+    uint32_t owner, last, size, pilot;
+};
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, kWave);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int lane) {  // lane is wave-uniform
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t o = shfl64(v, __lane_id() ^ d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+    for (int d = 32; d >= 1; d >>= 1) v += shfl64(v, __lane_id() ^ d);
+    return v;
+}
+
+// Slot within the part: reduce(h xor hp, S).
+__device__ __forceinline__ uint32_t local_slot(const DevMphf &m, uint64_t h, uint64_t hp) {
+    if (m.reduce_kind == kReduceMod) return (uint32_t)mod_reduce(h ^ hp, m.mod_slots, m.mod_magic);
+    return (uint32_t)(mulhi64(kMix, h ^ hp) & ((1ull << m.log2_slots) - 1));
+}
+
+__device__ __forceinline__ uint64_t pilot_hash(const DevMphf &m, uint32_t p) { return kMix * ((uint64_t)p ^ m.seed); }
+
+__device__ __forceinline__ bool is_taken(const uint32_t *bits, uint32_t q) { return (bits[q >> 5] >> (q & 31)) & 1u; }
+
+// bst[g] = index of the first sorted hash whose global bucket is >= g, for
+// g in [0, P*B]; flags[0] = 1 if two hashes are equal.
+__global__ void bucket_starts_k(const uint64_t *__restrict__ H, uint64_t n, DevMphf m, uint64_t *__restrict__ bst,
+                                uint32_t *__restrict__ flags) {
+    const uint64_t total = (uint64_t)m.parts * m.buckets;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t part;
+        const uint64_t g = bucket_of(m, H[i], part);
+        uint64_t first = 0;
+        if (i > 0) {
+            const uint64_t hp = H[i - 1];
+            if (hp == H[i]) flags[0] = 1u;
+            first = bucket_of(m, hp, part) + 1;
+        }
+        for (uint64_t b = first; b <= g; ++b) bst[b] = i;
+        if (i == n - 1)
+            for (uint64_t b = g + 1; b <= total; ++b) bst[b] = n;
+    }
+}
+
+// Largest bucket and largest part.
+__global__ void size_max_k(const uint64_t *__restrict__ bst, DevMphf m, unsigned long long *__restrict__ out) {
+    const uint64_t total = (uint64_t)m.parts * m.buckets;
+    uint64_t mb = 0, mp = 0;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = bst[g + 1] - bst[g];
+        mb = s > mb ? s : mb;
+        if (g % m.buckets == 0) {
+            const uint64_t ps = bst[g + m.buckets] - bst[g];
+            mp = ps > mp ? ps : mp;
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t ob = shfl64(mb, __lane_id() ^ d), op = shfl64(mp, __lane_id() ^ d);
+        mb = ob > mb ? ob : mb;
+        mp = op > mp ? op : mp;
+    }
+    if (__lane_id() == 0) {
+        atomicMax(&out[0], (unsigned long long)mb);
+        atomicMax(&out[1], (unsigned long long)mp);
+    }
+}
+
+// Sort key of bucket g: part, then size descending, then local id.
+__global__ void order_keys_k(const uint64_t *__restrict__ bst, DevMphf m, uint64_t max_size, uint32_t size_bits,
+                             uint32_t id_bits, uint64_t *__restrict__ keys) {
+    const uint64_t total = (uint64_t)m.parts * m.buckets;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t part = g / m.buckets, id = g - part * m.buckets;
+        const uint64_t s = bst[g + 1] - bst[g];
+        keys[g] = (part << (size_bits + id_bits)) | ((max_size - s) << id_bits) | id;
+    }
+}
+
+__device__ __forceinline__ void decode_key(uint64_t key, uint64_t max_size, uint32_t size_bits, uint32_t id_bits,
+                                           uint32_t &size, uint32_t &id) {
+    id = (uint32_t)(key & ((1ull << id_bits) - 1));
+    size = (uint32_t)(max_size - ((key >> id_bits) & ((1ull << size_bits) - 1)));
+}
+
+__global__ void ordered_sizes_k(const uint64_t *__restrict__ keys, uint64_t total, uint64_t max_size,
+                                uint32_t size_bits, uint32_t id_bits, uint64_t *__restrict__ sizes) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t s, id;
+        decode_key(keys[k], max_size, size_bits, id_bits, s, id);
+        sizes[k] = s;
+    }
+}
+
+// OH[ostart[k] + t] = hashes of the k-th bucket in search order.
+__global__ void scatter_ordered_k(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ ostart,
+                                  const uint64_t *__restrict__ bst, const uint64_t *__restrict__ H, DevMphf m,
+                                  uint64_t max_size, uint32_t size_bits, uint32_t id_bits, uint64_t *__restrict__ OH) {
+    const uint64_t total = (uint64_t)m.parts * m.buckets;
+    const uint32_t part_shift = size_bits + id_bits;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[k];
+        uint32_t s, id;
+        decode_key(key, max_size, size_bits, id_bits, s, id);
+        const uint64_t g = (key >> part_shift) * m.buckets + id;
+        const uint64_t src = bst[g], dst = ostart[k];
+        for (uint32_t t = 0; t < s; ++t) OH[dst + t] = H[src + t];
+    }
+}
+
+struct PlaceArgs {
+    DevMphf m;                  // geometry and seed
+    const uint64_t *H;          // n sorted hashes
+    const uint64_t *bst;        // P*B + 1 bucket starts into H
+    const uint64_t *okeys;      // P*B sorted order keys
+    const uint64_t *OH;         // hashes in search order (same part ranges as H)
+    uint64_t n;
+    uint64_t max_size;
+    uint32_t size_bits, id_bits;
+    uint64_t max_evictions;
+    uint8_t *pilots;            // P*B, zeroed
+    uint32_t *taken;            // P*S bits, zeroed
+    SlotRec *recs;              // grid * S scratch
+    uint32_t *big;              // grid * kMaxBucket scratch (slots of a large bucket)
+    uint32_t *next_part;        // work counter, zeroed
+    uint32_t *status;           // per part
+    uint64_t *evictions;        // per part
+};
+
+// Pairwise distinctness of up to 64 slots, key j in lane j (j < s): lane a
+// compares with lane a+d mod 64 for d = 1..32, which covers every pair.
+__device__ __forceinline__ bool distinct_lanes(uint32_t q, uint32_t s) {
+    const int lane = __lane_id();
+    bool dup = false;
+    for (int d = 1; d <= kWave / 2; ++d) {
+        if ((uint32_t)d >= s) break;
+        const int src = (lane + d) & (kWave - 1);
+        const uint32_t o = (uint32_t)__shfl((int)q, src, kWave);
+        dup |= (uint32_t)lane < s && (uint32_t)src < s && o == q;
+    }
+    return __ballot(dup) == 0;
+}
+
+struct LdsState {
+    uint64_t heap[kHeapCap];  // max-heap of (size << 32) | ~id
+    uint32_t heap_n;
+};
+
+// Heap operations run in every lane on the same values (LDS reads
+// broadcast); lane 0 writes.
+__device__ void heap_push(LdsState &st, uint64_t v) {
+    uint32_t i = st.heap_n;
+    while (i > 0) {
+        const uint32_t p = (i - 1) >> 1;
+        const uint64_t pv = st.heap[p];
+        if (pv >= v) break;
+        if (__lane_id() == 0) st.heap[i] = pv;
+        __builtin_amdgcn_wave_barrier();
+        i = p;
+    }
+    if (__lane_id() == 0) {
+        st.heap[i] = v;
+        st.heap_n = st.heap_n + 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ uint64_t heap_pop(LdsState &st) {
+    const uint64_t top = st.heap[0];
+    const uint32_t n = st.heap_n - 1;
+    const uint64_t v = st.heap[n];
+    uint32_t i = 0;
+    for (;;) {
+        const uint32_t c = 2 * i + 1;
+        if (c >= n) break;
+        uint32_t best = c;
+        if (c + 1 < n && st.heap[c + 1] > st.heap[c]) best = c + 1;
+        const uint64_t cv = st.heap[best];
+        if (cv <= v) break;
+        if (__lane_id() == 0) st.heap[i] = cv;
+        __builtin_amdgcn_wave_barrier();
+        i = best;
+    }
+    if (__lane_id() == 0) {
+        if (n) st.heap[i] = v;
+        st.heap_n = n;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return top;
+}
+
+// A 64-entry window of a read-only u64 stream held one entry per lane, with
+// the next window already in flight.
+struct Window {
+    const uint64_t *base;
+    uint64_t len, start;  // entries [start, start + 64) are in cur
+    uint64_t cur, next;
+
+    __device__ void load(uint64_t at, uint64_t &dst) const {
+        const uint64_t i = at + (uint64_t)__lane_id();
+        dst = i < len ? base[i] : 0;
+    }
+    __device__ void reset(uint64_t at) {
+        start = at;
+        load(at, cur);
+        load(at + kWave, next);
+    }
+    // bring entry `at` into cur (at >= start)
+    __device__ void seek(uint64_t at) {
+        if (at >= start + 2 * kWave) {
+            reset(at);
+        } else if (at >= start + kWave) {
+            cur = next;
+            start += kWave;
+            load(start + kWave, next);
+        }
+    }
+    __device__ uint64_t get(uint64_t at) const { return bcast64(cur, (int)(at - start)); }
+};
+
+// One wavefront per workgroup; a persistent grid takes parts from a counter.
+__global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
+    extern __shared__ uint32_t bits[];  // S bits of the current part
+    __shared__ LdsState st;
+    const DevMphf &m = a.m;
+    const int lane = __lane_id();
+    const uint32_t S = m.reduce_kind == kReduceMod ? m.mod_slots : (1u << m.log2_slots);
+    const uint32_t words = (S + 31) / 32;
+    const uint32_t B = m.buckets;
+    SlotRec *recs = a.recs + (uint64_t)blockIdx.x * S;
+    uint32_t *big = a.big + (uint64_t)blockIdx.x * kMaxBucket;
+
+    for (;;) {
+        uint32_t p = 0;
+        if (lane == 0) p = atomicAdd(a.next_part, 1u);
+        p = (uint32_t)__builtin_amdgcn_readfirstlane((int)p);
+        if (p >= m.parts) break;
+
+        for (uint32_t w = lane; w < words; w += kWave) bits[w] = 0u;
+        if (lane == 0) st.heap_n = 0;
+        __builtin_amdgcn_wave_barrier();
+
+        const uint64_t gb0 = (uint64_t)p * B;
+        uint64_t k = gb0;                    // next entry of the search order
+        const uint64_t kend = gb0 + B;
+        uint64_t c = a.bst[gb0];             // its first hash in OH
+        Window ow{a.okeys, kend, 0, 0, 0};
+        ow.reset(k);
+        // hashes: 128 entries [hw.start, hw.start + 128) in two windows
+        Window hw{a.OH, a.n, 0, 0, 0};
+        hw.reset(c);
+        uint64_t hw2 = 0;
+        hw.load(c + 2 * kWave, hw2);
+        uint64_t placed = 0, ev = 0;
+        uint32_t status = kPlaceOk;
+        const uint64_t max_iter = (uint64_t)B + a.max_evictions + 2;
+
+        for (uint64_t iter = 0;; ++iter) {
+            if (iter > max_iter) { status = kPlaceFailed; break; }
+            // next bucket: the larger of the order's head and the heap's top
+            uint32_t s = 0, id = 0;
+            bool from_order = false;
+            if (k < kend) {
+                ow.seek(k);
+                decode_key(ow.get(k), a.max_size, a.size_bits, a.id_bits, s, id);
+                from_order = s > 0;
+            }
+            if (st.heap_n > 0) {
+                const uint64_t head = from_order ? (((uint64_t)s << 32) | (0xffffffffu - id)) : 0;
+                if (st.heap[0] > head) {
+                    const uint64_t v = heap_pop(st);
+                    s = (uint32_t)(v >> 32);
+                    id = 0xffffffffu - (uint32_t)v;
+                    from_order = false;
+                }
+            } else if (!from_order) {
+                break;  // every bucket placed
+            }
+            const bool small = s <= kWave;
+            const uint64_t *src;
+            uint64_t h0 = 0;  // key `lane` of a small bucket
+            if (from_order) {
+                src = a.OH + c;
+                if (small) {
+                    if (c >= hw.start + kWave) {
+                        if (c >= hw.start + 2 * kWave) {
+                            hw.reset(c);
+                            hw.load(c + 2 * kWave, hw2);
+                        } else {
+                            hw.cur = hw.next;
+                            hw.next = hw2;
+                            hw.start += kWave;
+                            hw.load(hw.start + 2 * kWave, hw2);
+                        }
+                    }
+                    const uint32_t o = (uint32_t)(c - hw.start) + (uint32_t)lane;  // < 128
+                    const uint64_t x0 = shfl64(hw.cur, (int)(o & 63)), x1 = shfl64(hw.next, (int)(o & 63));
+                    h0 = o < (uint32_t)kWave ? x0 : x1;
+                }
+                c += s;
+                ++k;
+            } else {
+                src = a.H + a.bst[gb0 + id];
+                if (small && (uint32_t)lane < s) h0 = src[lane];
+            }
+            if (!small && s > kMaxBucket) { status = kPlaceTooLarge; break; }
+
+            int chosen = -1;
+            // 1) smallest pilot with free, distinct slots
+            if (small) {
+                for (int round = 0; round < 4 && chosen < 0; ++round) {
+                    const uint32_t pl = (uint32_t)(round * kWave + lane);
+                    const uint64_t hp = pilot_hash(m, pl);
+                    bool free = true;
+                    for (uint32_t j = 0; j < s; ++j) {
+                        const uint64_t hj = bcast64(h0, (int)j);
+                        if (free && is_taken(bits, local_slot(m, hj, hp))) free = false;
+                        if ((j & 3) == 3 && __ballot(free) == 0) break;
+                    }
+                    uint64_t cand = __ballot(free);
+                    while (cand) {
+                        const int lbit = __builtin_ctzll(cand);
+                        cand &= cand - 1;
+                        const uint32_t pc = (uint32_t)(round * kWave + lbit);
+                        // tentative: set the bits; a key that finds its bit already
+                        // set collides with a sibling (all slots were free)
+                        uint32_t myq = 0;
+                        bool mine = false, dup = false;
+                        if ((uint32_t)lane < s) {
+                            myq = local_slot(m, h0, pilot_hash(m, pc));
+                            const uint32_t old = atomicOr(&bits[myq >> 5], 1u << (myq & 31));
+                            if (old & (1u << (myq & 31))) dup = true; else mine = true;
+                        }
+                        if (__ballot(dup) == 0) { chosen = (int)pc; break; }
+                        if (mine) atomicAnd(&bits[myq >> 5], ~(1u << (myq & 31)));
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            } else {
+                for (uint32_t pc = 0; pc < 256 && chosen < 0; ++pc) {
+                    const uint64_t hpc = pilot_hash(m, pc);
+                    bool any_taken = false;
+                    for (uint32_t t = lane; t < s; t += kWave) any_taken |= is_taken(bits, local_slot(m, src[t], hpc));
+                    if (__ballot(any_taken)) continue;
+                    bool dup = false;
+                    uint32_t mine = 0;
+                    for (uint32_t t = lane, r = 0; t < s; t += kWave, ++r) {
+                        const uint32_t qq = local_slot(m, src[t], hpc);
+                        const uint32_t old = atomicOr(&bits[qq >> 5], 1u << (qq & 31));
+                        if (old & (1u << (qq & 31))) dup = true; else mine |= 1u << r;
+                    }
+                    if (__ballot(dup) == 0) { chosen = (int)pc; break; }
+                    for (uint32_t t = lane, r = 0; t < s; t += kWave, ++r)
+                        if (mine & (1u << r)) {
+                            const uint32_t qq = local_slot(m, src[t], hpc);
+                            atomicAnd(&bits[qq >> 5], ~(1u << (qq & 31)));
+                        }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+
+            if (chosen < 0) {
+                // 2) least weighted collisions, never touching the recent ones.
+                // The slot records read below were written by earlier
+                // placements of this wavefront: wait for those stores.
+                __threadfence_block();
+                if (small) {
+                    uint64_t keyr[4];
+                    for (int round = 0; round < 4; ++round) {
+                        const uint32_t pl = (uint32_t)(round * kWave + lane);
+                        const uint64_t hp = pilot_hash(m, pl);
+                        uint64_t cost = 0;
+                        bool ok = true;
+                        for (uint32_t j = 0; j < s; ++j) {
+                            const uint32_t qq = local_slot(m, bcast64(h0, (int)j), hp);
+                            if (ok && is_taken(bits, qq)) {
+                                const SlotRec rec = recs[qq];
+                                if ((uint64_t)rec.last + kRecent > placed) ok = false;
+                                cost += (uint64_t)rec.size * rec.size;
+                            }
+                        }
+                        keyr[round] = ok ? ((cost << 8) | pl) : ~0ull;
+                    }
+                    // the least (cost, pilot) whose slots are distinct
+                    for (int tries = 0; tries < 256; ++tries) {
+                        uint64_t mn = keyr[0];
+                        for (int r = 1; r < 4; ++r) mn = keyr[r] < mn ? keyr[r] : mn;
+                        mn = wave_min64(mn);
+                        if (mn == ~0ull) break;
+                        const uint32_t pc = (uint32_t)(mn & 255);
+                        const uint32_t qq = (uint32_t)lane < s ? local_slot(m, h0, pilot_hash(m, pc)) : 0u;
+                        if (distinct_lanes(qq, s)) { chosen = (int)pc; break; }
+                        if ((uint32_t)lane == (pc & 63)) keyr[pc >> 6] = ~0ull;
+                    }
+                } else {
+                    uint64_t best = ~0ull;
+                    for (uint32_t pc = 0; pc < 256; ++pc) {
+                        const uint64_t hpc = pilot_hash(m, pc);
+                        uint64_t cost = 0;
+                        bool ok = true;
+                        for (uint32_t t = lane; t < s; t += kWave) {
+                            const uint32_t qq = local_slot(m, src[t], hpc);
+                            if (is_taken(bits, qq)) {
+                                const SlotRec rec = recs[qq];
+                                if ((uint64_t)rec.last + kRecent > placed) ok = false;
+                                cost += (uint64_t)rec.size * rec.size;
+                            }
+                        }
+                        if (__ballot(!ok)) continue;
+                        cost = wave_sum64(cost);
+                        if (cost >= best) continue;
+                        // distinct: write the slots to scratch, compare all pairs
+                        for (uint32_t t = lane; t < s; t += kWave) big[t] = local_slot(m, src[t], hpc);
+                        __threadfence_block();
+                        bool dup = false;
+                        for (uint32_t t = lane; t < s && !dup; t += kWave) {
+                            const uint32_t qt = big[t];
+                            for (uint32_t u = t + 1; u < s; ++u)
+                                if (big[u] == qt) { dup = true; break; }
+                        }
+                        if (__ballot(dup) == 0) {
+                            best = cost;
+                            chosen = (int)pc;
+                        }
+                    }
+                }
+                if (chosen < 0) { status = kPlaceFailed; break; }
+                // evict every owner the chosen slots hit, key by key
+                const uint64_t hpc = pilot_hash(m, (uint32_t)chosen);
+                for (uint32_t j = 0; j < s; ++j) {
+                    const uint64_t hj = small ? bcast64(h0, (int)j) : src[j];
+                    const uint32_t qq = local_slot(m, hj, hpc);
+                    if (!is_taken(bits, qq)) continue;
+                    const SlotRec rec = recs[qq];
+                    if (rec.owner >= B || rec.size == 0 || rec.size > kMaxBucket || rec.pilot > 255) {
+                        status = kPlaceCorrupt;  // never expected: a record that no placement wrote
+                        break;
+                    }
+                    const uint64_t *oh = a.H + a.bst[gb0 + rec.owner];
+                    const uint64_t hpo = pilot_hash(m, rec.pilot);
+                    for (uint32_t t = lane; t < rec.size; t += kWave) {
+                        const uint32_t qo = local_slot(m, oh[t], hpo);
+                        atomicAnd(&bits[qo >> 5], ~(1u << (qo & 31)));
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (st.heap_n >= kHeapCap) { status = kPlaceHeapFull; break; }
+                    heap_push(st, ((uint64_t)rec.size << 32) | (0xffffffffu - rec.owner));
+                    ++ev;
+                }
+                if (status != kPlaceOk) break;
+                // the bucket's bits (phase 1 set them already)
+                for (uint32_t t = lane; t < s; t += kWave) {
+                    const uint32_t qq = local_slot(m, small ? h0 : src[t], hpc);
+                    atomicOr(&bits[qq >> 5], 1u << (qq & 31));
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+
+            // slot records and pilot of the placed bucket
+            ++placed;
+            const uint64_t hpc = pilot_hash(m, (uint32_t)chosen);
+            const SlotRec rec{id, (uint32_t)placed, s, (uint32_t)chosen};
+            for (uint32_t t = lane; t < s; t += kWave) recs[local_slot(m, small ? h0 : src[t], hpc)] = rec;
+            if (lane == 0) a.pilots[gb0 + id] = (uint8_t)chosen;
+            if (ev > a.max_evictions) { status = kPlaceFailed; break; }
+        }
+
+        // the part's taken slots into the global bitvector (P*S bits; parts
+        // start on a word boundary: S is a multiple of 32 or there is one part)
+        __builtin_amdgcn_wave_barrier();
+        if (status == kPlaceOk) {
+            const uint64_t wbase = (uint64_t)p * S / 32;
+            for (uint32_t w = lane; w < words; w += kWave) {
+                uint32_t v = bits[w];
+                if (w == words - 1 && (S & 31)) v &= (1u << (S & 31)) - 1;
+                a.taken[wbase + w] = v;
+            }
+        }
+        if (lane == 0) {
+            a.status[p] = status;
+            a.evictions[p] = ev;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace ptrhash
+
+// ---------------------------------------------------------------------------
+// Host side: buffers, passes, reseeding.
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "builder.h"
+#include "errors.h"
+
+namespace {
+
+using ptrhash::set_error;
+
+__global__ void hash_keys_gpu_k(const uint64_t *__restrict__ keys, uint64_t n, uint64_t *__restrict__ out) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = ptrhash::hash_u64(keys[i]);
+}
+
+struct DevBufs {
+    std::vector<void *> p;
+    ~DevBufs() {
+        for (void *x : p)
+            if (x) (void)hipFree(x);
+    }
+    template <typename T>
+    hipError_t get(T **out, uint64_t count) {
+        void *x = nullptr;
+        const hipError_t e = hipMalloc(&x, count ? count * sizeof(T) : 1);
+        if (e == hipSuccess) p.push_back(x);
+        *out = static_cast<T *>(x);
+        return e;
+    }
+};
+
+uint32_t bit_width(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) : 0u; }
+
+#define HIP_OR_FAIL(expr, what)                                                                      \
+    do {                                                                                             \
+        const hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                        \
+            return set_error(e_ == hipErrorOutOfMemory ? PTRHASH_E_NOMEM : PTRHASH_E_HIP, "%s: %s", \
+                             what, hipGetErrorString(e_));                                           \
+    } while (0)
+
+constexpr int kMaxSeeds = 16;
+constexpr uint64_t kEvictionFactor = 10;
+
+int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
+              ptrhash_build_info *info, hipStream_t stream) {
+    using namespace ptrhash;
+    if (!keys || !params || !pilots) return set_error(PTRHASH_E_INVAL, "NULL argument");
+    if (int rc = check_build_params(n, params, PTRHASH_KEY_U64)) return rc;
+    if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
+    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
+    const uint64_t S = mod ? params->slots : 1ull << params->log2_slots;
+    const uint64_t P = params->num_parts, B = params->buckets_per_part, total = P * B;
+    const uint64_t words = (S + 31) / 32;
+    if (P > 1 && S % 32) return set_error(PTRHASH_E_RANGE, "device placement: S must be a multiple of 32");
+
+    int dev = 0, cus = 0, lds_max = 0;
+    HIP_OR_FAIL(hipGetDevice(&dev), "device query");
+    HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device query");
+    HIP_OR_FAIL(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device query");
+    const size_t lds = words * sizeof(uint32_t);
+    if (lds + sizeof(LdsState) > (size_t)lds_max)
+        return set_error(PTRHASH_E_RANGE, "device placement: %llu slots per part exceed the LDS of one CU",
+                         (unsigned long long)S);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&place_k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    int per_cu = 0;
+    HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k, kWave, lds), "occupancy query");
+    if (per_cu < 1) return set_error(PTRHASH_E_RANGE, "device placement does not fit one CU");
+    const uint64_t grid = std::min<uint64_t>(P, (uint64_t)cus * (uint64_t)per_cu);
+
+    const bool timing = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
+    auto tick = std::chrono::steady_clock::now();
+    auto phase = [&](const char *name) {
+        if (!timing) return;
+        (void)hipStreamSynchronize(stream);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[build] %-10s %8.3f s\n", name, std::chrono::duration<double>(now - tick).count());
+        tick = now;
+    };
+
+    DevMphf m{};
+    m.n = n;
+    m.parts = (uint32_t)P;
+    m.buckets = (uint32_t)B;
+    m.log2_slots = mod ? 0 : params->log2_slots;
+    m.gamma = params->gamma;
+    m.reduce_kind = params->reduce_kind;
+    m.mod_slots = mod ? (uint32_t)S : 0;
+    m.mod_magic = mod ? ~0ull / S : 0;  // floor((2^64 - 1) / S) = floor(2^64 / S): S is not a power of two
+
+    DevBufs buf;
+    uint64_t *ha = nullptr, *hb = nullptr, *bst = nullptr, *ka = nullptr, *kb = nullptr, *ostart = nullptr;
+    unsigned long long *maxes = nullptr;
+    uint32_t *flags = nullptr;
+    HIP_OR_FAIL(buf.get(&ha, n), "device hashes");
+    HIP_OR_FAIL(buf.get(&hb, n), "device hashes");
+    HIP_OR_FAIL(buf.get(&bst, total + 1), "bucket starts");
+    HIP_OR_FAIL(buf.get(&maxes, 2), "device scalars");
+    HIP_OR_FAIL(buf.get(&flags, 1), "device scalars");
+
+    // hash and sort
+    hipLaunchKernelGGL(hash_keys_gpu_k, dim3(8192), dim3(256), 0, stream, keys, n, ha);
+    HIP_OR_FAIL(hipGetLastError(), "hash launch");
+    hipcub::DoubleBuffer<uint64_t> hdb(ha, hb);
+    size_t temp = 0;
+    HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, hdb, (size_t)n, 0, 64, stream), "sort sizing");
+    {
+        uint8_t *scratch = nullptr;
+        HIP_OR_FAIL(buf.get(&scratch, temp), "sort scratch");
+        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(scratch, temp, hdb, (size_t)n, 0, 64, stream), "sort");
+    }
+    const uint64_t *H = hdb.Current();
+    uint64_t *OH = hdb.Alternate();
+    phase("hash+sort");
+
+    // bucket starts, duplicates, largest bucket and part
+    HIP_OR_FAIL(hipMemsetAsync(flags, 0, sizeof(uint32_t), stream), "memset");
+    HIP_OR_FAIL(hipMemsetAsync(maxes, 0, 2 * sizeof(unsigned long long), stream), "memset");
+    hipLaunchKernelGGL(bucket_starts_k, dim3(8192), dim3(256), 0, stream, H, n, m, bst, flags);
+    HIP_OR_FAIL(hipGetLastError(), "bucket starts launch");
+    hipLaunchKernelGGL(size_max_k, dim3(4096), dim3(256), 0, stream, bst, m, maxes);
+    HIP_OR_FAIL(hipGetLastError(), "size launch");
+    uint32_t dup = 0;
+    unsigned long long mx[2] = {0, 0};
+    HIP_OR_FAIL(hipMemcpyAsync(&dup, flags, sizeof dup, hipMemcpyDeviceToHost, stream), "copy out");
+    HIP_OR_FAIL(hipMemcpyAsync(mx, maxes, sizeof mx, hipMemcpyDeviceToHost, stream), "copy out");
+    HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+    if (dup) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
+    if (mx[1] > S) return set_error(PTRHASH_E_BUILD, "a part holds more than S keys");
+    const uint64_t max_size = mx[0];
+    if (max_size > kMaxBucket)
+        return set_error(PTRHASH_E_RANGE, "device placement: a bucket of %llu keys (at most %u)",
+                         (unsigned long long)max_size, kMaxBucket);
+    const uint32_t size_bits = bit_width(max_size), id_bits = bit_width(B - 1), part_bits = bit_width(P - 1);
+    if (size_bits + id_bits + part_bits > 64) return set_error(PTRHASH_E_RANGE, "device placement: sort key width");
+    phase("starts");
+
+    // search order: per part, size descending, then bucket id
+    HIP_OR_FAIL(buf.get(&ka, total), "order keys");
+    HIP_OR_FAIL(buf.get(&kb, total), "order keys");
+    HIP_OR_FAIL(buf.get(&ostart, total), "order offsets");
+    hipLaunchKernelGGL(order_keys_k, dim3(8192), dim3(256), 0, stream, bst, m, max_size, size_bits, id_bits, ka);
+    HIP_OR_FAIL(hipGetLastError(), "order launch");
+    hipcub::DoubleBuffer<uint64_t> kdb(ka, kb);
+    const int end_bit = (int)(size_bits + id_bits + part_bits);
+    temp = 0;
+    HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, kdb, (size_t)total, 0, end_bit, stream),
+                "order sort sizing");
+    {
+        uint8_t *scratch = nullptr;
+        HIP_OR_FAIL(buf.get(&scratch, temp), "order sort scratch");
+        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(scratch, temp, kdb, (size_t)total, 0, end_bit, stream),
+                    "order sort");
+    }
+    const uint64_t *okeys = kdb.Current();
+    uint64_t *osize = kdb.Alternate();
+    hipLaunchKernelGGL(ordered_sizes_k, dim3(8192), dim3(256), 0, stream, okeys, total, max_size, size_bits, id_bits,
+                       osize);
+    HIP_OR_FAIL(hipGetLastError(), "sizes launch");
+    temp = 0;
+    HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(nullptr, temp, osize, ostart, (int64_t)total, stream), "scan sizing");
+    {
+        uint8_t *scratch = nullptr;
+        HIP_OR_FAIL(buf.get(&scratch, temp), "scan scratch");
+        HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(scratch, temp, osize, ostart, (int64_t)total, stream), "scan");
+    }
+    hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream, okeys, ostart, bst, H, m, max_size,
+                       size_bits, id_bits, OH);
+    HIP_OR_FAIL(hipGetLastError(), "scatter launch");
+    phase("order");
+
+    // the search, reseeding failed builds
+    uint8_t *dpil = nullptr;
+    uint32_t *dtaken = nullptr, *dbig = nullptr, *dnext = nullptr, *dstatus = nullptr;
+    SlotRec *drecs = nullptr;
+    uint64_t *dev_ev = nullptr;
+    const uint64_t taken_words = (P * S + 63) / 64 * 2;  // u32 words, whole u64 words
+    HIP_OR_FAIL(buf.get(&dpil, total), "pilots");
+    HIP_OR_FAIL(buf.get(&dtaken, taken_words), "taken bits");
+    HIP_OR_FAIL(buf.get(&drecs, grid * S), "slot records");
+    HIP_OR_FAIL(buf.get(&dbig, grid * (uint64_t)kMaxBucket), "bucket scratch");
+    HIP_OR_FAIL(buf.get(&dnext, 1), "work counter");
+    HIP_OR_FAIL(buf.get(&dstatus, P), "part status");
+    HIP_OR_FAIL(buf.get(&dev_ev, P), "part evictions");
+    std::vector<uint32_t> status(P);
+    std::vector<uint64_t> evs(P);
+    ptrhash_build_info local{};
+    local.max_bucket_size = max_size;
+    for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
+        local.attempts = (uint64_t)attempt + 1;
+        m.seed = params->seed + (uint64_t)attempt;
+        HIP_OR_FAIL(hipMemsetAsync(dpil, 0, total, stream), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(dtaken, 0, taken_words * sizeof(uint32_t), stream), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(dnext, 0, sizeof(uint32_t), stream), "memset");
+        PlaceArgs a{};
+        a.m = m;
+        a.H = H;
+        a.bst = bst;
+        a.okeys = okeys;
+        a.OH = OH;
+        a.n = n;
+        a.max_size = max_size;
+        a.size_bits = size_bits;
+        a.id_bits = id_bits;
+        a.max_evictions = kEvictionFactor * S;
+        a.pilots = dpil;
+        a.taken = dtaken;
+        a.recs = drecs;
+        a.big = dbig;
+        a.next_part = dnext;
+        a.status = dstatus;
+        a.evictions = dev_ev;
+        hipLaunchKernelGGL(place_k, dim3((uint32_t)grid), dim3(kWave), lds, stream, a);
+        HIP_OR_FAIL(hipGetLastError(), "search launch");
+        HIP_OR_FAIL(hipMemcpyAsync(status.data(), dstatus, P * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                    "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(evs.data(), dev_ev, P * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                    "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(stream), "search");
+        bool failed = false;
+        for (uint64_t p = 0; p < P; ++p) {
+            if (status[p] == kPlaceHeapFull || status[p] == kPlaceTooLarge)
+                return set_error(PTRHASH_E_RANGE, "device placement: part %llu outside the search's limits (%u)",
+                                 (unsigned long long)p, status[p]);
+            if (status[p] > kPlaceTooLarge)
+                return set_error(PTRHASH_E_HIP, "device placement: inconsistent slot record in part %llu",
+                                 (unsigned long long)p);
+            failed |= status[p] != kPlaceOk;
+        }
+        phase("search");
+        if (failed) continue;
+        local.evictions = local.max_part_evictions = 0;
+        for (uint64_t p = 0; p < P; ++p) {
+            local.evictions += evs[p];
+            local.max_part_evictions = std::max(local.max_part_evictions, evs[p]);
+        }
+        std::vector<uint64_t> taken;
+        try {
+            taken.resize(taken_words / 2);
+        } catch (const std::bad_alloc &) {
+            return set_error(PTRHASH_E_NOMEM, "host taken-slot bitvector");
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(pilots, dpil, total, hipMemcpyDeviceToHost, stream), "pilots to host");
+        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), dtaken, taken_words * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                    "taken bits to host");
+        HIP_OR_FAIL(hipStreamSynchronize(stream), "copy out");
+        ptrhash_params out = *params;
+        out.seed = m.seed;
+        if (int rc = remap_from_taken(&out, taken, remap)) return rc;
+        phase("remap");
+        params->seed = m.seed;
+        if (info) *info = local;
+        return PTRHASH_OK;
+    }
+    if (info) *info = local;
+    return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
+}
+
+}  // namespace
+
+extern "C" {
+
+PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
+                                      void *remap, ptrhash_build_info *info, hipStream_t stream) {
+    try {
+        return build_gpu(keys, n, params, pilots, remap, info, stream);
+    } catch (const std::bad_alloc &) {
+        return ptrhash::set_error(PTRHASH_E_NOMEM, "host allocation failed during construction");
+    }
+}
+
+}  // extern "C"

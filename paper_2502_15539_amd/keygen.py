@@ -139,12 +139,22 @@ def query_stream(n: int, key_seed: int = KEY_SEED, order_seed: int = ORDER_SEED,
     return _parallel_fill(out, lambda i: splitmix64(key_seed, perm(i)), start)
 
 
+def query_stream_at(n: int, positions: np.ndarray, key_seed: int = KEY_SEED,
+                    order_seed: int = ORDER_SEED) -> np.ndarray:
+    """Entries at arbitrary ``positions`` of the shuffled member stream."""
+    return splitmix64(key_seed, Permutation(n, order_seed)(np.asarray(positions, dtype=np.uint64)))
+
+
 STR_MIN, STR_MAX = 10, 50
 STR_PAD = 64
 
 
 def string_lengths(count: int, seed: int, start: int = 0) -> np.ndarray:
-    r = splitmix64(seed, np.arange(start, start + count, dtype=np.uint64))
+    return string_lengths_at(np.arange(start, start + count, dtype=np.uint64), seed)
+
+
+def string_lengths_at(indices: np.ndarray, seed: int) -> np.ndarray:
+    r = splitmix64(seed, np.asarray(indices, dtype=np.uint64))
     return (np.uint64(STR_MIN) + r % np.uint64(STR_MAX - STR_MIN + 1)).astype(np.int64)
 
 
@@ -185,6 +195,28 @@ def strings(count: int, seed: int = KEY_SEED, start: int = 0):
         for lo in chunks:
             work(lo)
     return data, offsets
+
+
+def strings_at(indices: np.ndarray, seed: int = KEY_SEED):
+    """Strings with arbitrary indices of the random-string stream, packed in
+    the given order (same layout as ``strings``)."""
+    idx = np.asarray(indices, dtype=np.uint64)
+    lens = string_lengths_at(idx, seed)
+    offsets = np.zeros(len(idx) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    total = int(offsets[-1])
+    owner = np.repeat(idx, lens)
+    pos_in = np.arange(total, dtype=np.int64) - np.repeat(offsets[:-1].astype(np.int64), lens)
+    r = splitmix64(seed ^ 0x2545F4914F6CDD1D, owner * np.uint64(64) + pos_in.astype(np.uint64))
+    data = np.zeros(total + STR_PAD, dtype=np.uint8)
+    data[:total] = (np.uint64(0x20) + (r & np.uint64(0xFF)) % np.uint64(95)).astype(np.uint8)
+    return data, offsets
+
+
+def string_query_stream_at(count: int, positions: np.ndarray, seed: int = KEY_SEED,
+                           order_seed: int = ORDER_SEED):
+    """Entries at arbitrary ``positions`` of the shuffled string stream."""
+    return strings_at(Permutation(count, order_seed)(np.asarray(positions, dtype=np.uint64)), seed)
 
 
 def string_query_stream(count: int, seed: int = KEY_SEED, order_seed: int = ORDER_SEED):

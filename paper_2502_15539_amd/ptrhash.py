@@ -115,6 +115,8 @@ _SIGS = {
                                     C.POINTER(BuildInfo)]),
     "ptrhash_build_u64_device": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                            C.c_int, C.POINTER(BuildInfo), C.c_void_p]),
+    "ptrhash_build_u64_gpu": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                        C.POINTER(BuildInfo), C.c_void_p]),
     "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
@@ -204,6 +206,7 @@ class Built:
     pilots: np.ndarray
     remap: np.ndarray
     info: BuildInfo
+    placement: str = "host"  # where the pilot search ran
 
     @property
     def bits_per_key(self) -> float:
@@ -221,17 +224,34 @@ def build_u64(keys: np.ndarray, params: Params | None = None, threads: int = 0, 
     return Built(p, pilots, remap, info)
 
 
-def build_u64_device(keys, params: Params | None = None, threads: int = 0, stream=None, **kw) -> Built:
-    """Build from u64 keys in device memory (a cuda int64/uint64 tensor):
-    hashing and sorting on the device, pilot search on host threads."""
+def build_u64_device(keys, params: Params | None = None, threads: int = 0, stream=None, placement: str = "auto",
+                     **kw) -> Built:
+    """Build from u64 keys in device memory (a cuda int64/uint64 tensor).
+
+    placement: "device" runs the pilot search on the GPU too
+    (ptrhash_build_u64_gpu); "host" hashes and sorts on the GPU and searches
+    on host threads (ptrhash_build_u64_device); "auto" takes the device
+    search unless the parameters are outside its limits (E_RANGE). Every
+    choice gives the same MPHF; ``Built.placement`` says which ran."""
+    if placement not in ("auto", "device", "host"):
+        raise ValueError("placement must be 'auto', 'device' or 'host'")
     n = keys.numel()
-    p = (params if params is not None else params_default(n, **kw)).copy()
-    pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
-    remap = np.zeros(remap_bytes(p), dtype=np.uint8)
+    p0 = (params if params is not None else params_default(n, **kw)).copy()
+    pilots = np.zeros(p0.num_parts * p0.buckets_per_part, dtype=np.uint8)
+    remap = np.zeros(remap_bytes(p0), dtype=np.uint8)
     info = BuildInfo()
+    if placement != "host":
+        p = p0.copy()
+        rc = lib().ptrhash_build_u64_gpu(_dev_ptr(keys), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
+                                         C.byref(info), _stream(stream))
+        if rc == 0:
+            return Built(p, pilots, remap, info, "device")
+        if placement == "device" or rc != E_RANGE:
+            _check(rc, "ptrhash_build_u64_gpu")
+    p = p0.copy()
     _check(lib().ptrhash_build_u64_device(_dev_ptr(keys), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
                                           int(threads), C.byref(info), _stream(stream)), "ptrhash_build_u64_device")
-    return Built(p, pilots, remap, info)
+    return Built(p, pilots, remap, info, "host")
 
 
 def build_bytes(data: np.ndarray, offsets: np.ndarray, params: Params | None = None, threads: int = 0,

@@ -206,3 +206,20 @@ def test_hash128_params_rule():
     with pytest.raises(P.PtrHashError) as e:
         m.load(p, np.zeros(p.num_parts * p.buckets_per_part, np.uint8), np.zeros(P.remap_bytes(p), np.uint8))
     assert e.value.code == P.E_INVAL
+
+
+def test_device_build_rejects_bad_arguments_before_any_device_call():
+    import ctypes as C
+
+    p = P.params_default(1000)
+    pil = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    rm = np.zeros(P.remap_bytes(p), dtype=np.uint8)
+    f = P.lib().ptrhash_build_u64_gpu
+    # NULL keys
+    assert f(None, 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
+    # n disagrees with params->n (checked before the keys are touched)
+    assert f(C.c_void_p(16), 999, C.byref(p), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
+    # byte-key params
+    q = P.params_default(1000, key_kind=P.KEY_BYTES)
+    assert f(C.c_void_p(16), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
+    assert b"key_kind" in P.lib().ptrhash_last_error()

@@ -1,0 +1,129 @@
+"""Construction with the pilot search on the device.
+
+The oracle builds the same keys with the same parameters; the device build
+must give the same seed, the same pilots and the same remap bytes. Beyond
+the oracle's reach (10^8 keys) the device search must equal the library's
+host search byte for byte.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_15539_amd import keygen as K
+from paper_2502_15539_amd import ptrhash as P
+
+from .mphf_pairs import lib_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(keys):
+    return torch.from_numpy(keys.view(np.int64)).to(DEV)
+
+
+def same(b, m, remap_kind=P.REMAP_CLEF):
+    assert b.placement == "device"
+    assert b.params.seed == m.params.seed
+    assert np.array_equal(b.pilots, m.pilots)
+    want = m.clef if remap_kind == P.REMAP_CLEF else m.F.astype(np.uint32).view(np.uint8)
+    assert np.array_equal(b.remap, want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 1000, 40_000, 250_000, 2_000_000])
+def test_device_search_equals_oracle_default(n):
+    keys = K.u64_keys(n, seed=1000 + n % 97)
+    say(f"[gpu-build] default n={n}")
+    b = P.build_u64_device(dev(keys), placement="device")
+    m = O.build_u64(keys)
+    assert (b.params.num_parts, b.params.log2_slots, b.params.buckets_per_part) == \
+        (m.params.num_parts, m.params.log2_slots, m.params.buckets_per_part)
+    same(b, m)
+    assert b.info.max_bucket_size == m.stats.max_bucket_size
+
+
+@pytest.mark.parametrize("preset,lam,gamma,remap", [(P.PRESET_FAST, 3.0, O.GAMMA_LINEAR, P.REMAP_U32),
+                                                    (P.PRESET_COMPACT, 4.0, O.GAMMA_CUBIC, P.REMAP_CLEF)])
+def test_device_search_equals_oracle_presets(preset, lam, gamma, remap):
+    n = 300_000
+    keys = K.u64_keys(n, seed=77)
+    say(f"[gpu-build] preset={preset} n={n}")
+    b = P.build_u64_device(dev(keys), placement="device", preset=preset, index_bits=32)
+    m = O.build_u64(keys, lam=lam, gamma=gamma)
+    assert b.params.remap_kind == remap
+    same(b, m, remap)
+
+
+@pytest.mark.parametrize("n", [1, 3, 1000, 77_777])
+def test_device_search_single_part_mod(n):
+    keys = K.u64_keys(n, seed=55)
+    say(f"[gpu-build] single-part mod n={n}")
+    p = P.params_default(n, P.PRESET_DEFAULT | P.PRESET_SINGLE_MOD)
+    b = P.build_u64_device(dev(keys), params=p, placement="device")
+    m = O.build_u64(keys, params=O.params_single_mod(n))
+    same(b, m)
+
+
+def test_device_search_reseeds_like_oracle():
+    """Little slack (lambda = 4 with S = 2^15 for 20000 keys) makes
+    attempts fail; the device must step through the seeds like the oracle."""
+    n = 20_000
+    keys = K.u64_keys(n, seed=4)
+    o = O.params_explicit(n, 1, 15, 5000, seed=0)
+    try:
+        m = O.build_u64(keys, params=o)
+    except O.BuildError:
+        pytest.skip("oracle could not build this instance")
+    p = lib_params(m)
+    p.seed = 0
+    p.index_bits = 32
+    say(f"[gpu-build] reseed n={n}")
+    b = P.build_u64_device(dev(keys), params=p, placement="device")
+    same(b, m)
+    assert b.info.attempts == m.stats.attempts
+
+
+def test_device_search_errors():
+    keys = K.u64_keys(5000, seed=3)
+    keys[4000] = keys[12]
+    say("[gpu-build] duplicates")
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_u64_device(dev(keys), placement="device")
+    assert e.value.code == P.E_DUPLICATE
+    # S = 2^21 needs 256 KiB of LDS per part: outside the device search
+    n = 300_000
+    o = O.params_explicit(n, 1, 21, 150_000)
+    p = P.params_default(n)
+    p.num_parts, p.log2_slots, p.buckets_per_part, p.remap_len = 1, 21, 150_000, o.remap_len
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_u64_device(dev(K.u64_keys(n)), params=p, placement="device")
+    assert e.value.code == P.E_RANGE
+    b = P.build_u64_device(dev(K.u64_keys(n)), params=p, placement="auto")
+    assert b.placement == "host"
+
+
+def test_device_search_equals_host_search_1e8():
+    n = 10**8
+    say(f"[gpu-build] n={n}: device keys, device search vs host search")
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
+    t0 = time.time()
+    bd = P.build_u64_device(keys, placement="device")
+    t1 = time.time()
+    bh = P.build_u64_device(keys, placement="host", threads=min(16, os.cpu_count() or 1))
+    t2 = time.time()
+    say(f"[gpu-build] device {t1 - t0:.2f} s, host search {t2 - t1:.2f} s, evictions {bd.info.evictions}")
+    assert bd.placement == "device" and bh.placement == "host"
+    assert bd.params.seed == bh.params.seed
+    assert bd.info.evictions == bh.info.evictions
+    assert np.array_equal(bd.pilots, bh.pilots) and np.array_equal(bd.remap, bh.remap)

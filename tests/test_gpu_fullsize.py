@@ -1,0 +1,157 @@
+"""Parity at the full benchmark sizes, in the launch configuration that the
+benchmark times.
+
+At 10^9 u64 keys and 3*10^8 strings the oracle cannot build the MPHF inside
+a test, so the tables come from the library's builder (which the CPU tests
+show to be byte-identical to the oracle's construction at every size the
+oracle can build). The checks here:
+
+* parameters equal the oracle's parameter rule;
+* the kernel choice is the one the benchmark's autotuner picks, over the same
+  candidate list, and the plain one-key-per-lane kernel agrees with it on
+  every output;
+* all members map bijectively onto [0, n) (a property that holds at any
+  size);
+* the oracle's query formula, evaluated one key at a time on sampled
+  positions of the stream (the first and last 2^18 and 2^20 random ones),
+  gives exactly the GPU's indices. The sampled keys are regenerated on the
+  host from the seeded generators, not read back from the device;
+* non-members: 2^20 of them, every output equal to the oracle's.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_15539_amd import autotune
+from paper_2502_15539_amd import keygen as K
+from paper_2502_15539_amd import ptrhash as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+EDGE = 1 << 18
+RANDOM = 1 << 20
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def threads():
+    return min(16, os.cpu_count() or 1)
+
+
+def sample_positions(n, seed):
+    rng = np.random.default_rng(seed)
+    pos = np.concatenate([np.arange(min(EDGE, n)), np.arange(max(0, n - EDGE), n),
+                          rng.integers(0, n, RANDOM)])
+    return pos.astype(np.uint64)
+
+
+def oracle_of(built):
+    p = built.params
+    op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    return O.Mphf(op, built.pilots, None, built.remap, None)
+
+
+def check_params(p, n):
+    ref = O.params_for(n)
+    assert (p.num_parts, p.log2_slots, p.buckets_per_part) == (ref.num_parts, ref.log2_slots, ref.buckets_per_part)
+    assert p.gamma == P.GAMMA_CUBIC and p.remap_kind == P.REMAP_CLEF
+
+
+def bijective(out, n):
+    o = out.long()
+    assert int(o.min()) >= 0 and int(o.max()) < n
+    seen = torch.zeros(n, dtype=torch.bool, device=out.device)
+    seen[o] = True
+    return bool(seen.all())
+
+
+def to_u64(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if a.dtype == np.int64 else a.view(np.uint32).astype(np.uint64)
+
+
+def tuned(mphf, run, n_q, key_kind):
+    best, _ = autotune.tune(torch, mphf, run, n_q, cands=autotune.candidates_for(key_kind), use_cache=False)
+    say(f"[fullsize] tuned choice {best}")
+    return best
+
+
+def test_u64_1e9_default():
+    n = 10**9
+    say(f"[fullsize] u64 n={n}: device keys + library build")
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
+    built = P.build_u64_device(keys, index_bits=64, threads=threads())
+    del keys
+    torch.cuda.empty_cache()
+    check_params(built.params, n)
+    mphf = P.Mphf.from_built(built)
+    q = P.gen_query_stream(torch.empty(n, dtype=torch.int64, device=DEV), n, K.KEY_SEED, K.ORDER_SEED)
+    out = torch.empty(n, dtype=torch.int64, device=DEV)
+    tuned(mphf, lambda: mphf.query_into(q, out), n, P.KEY_U64)
+    mphf.query_into(q, out)
+    torch.cuda.synchronize()
+    say("[fullsize] u64 bijection")
+    assert bijective(out, n)
+
+    say("[fullsize] u64 sampled oracle parity")
+    pos = sample_positions(n, 11)
+    qs = K.query_stream_at(n, pos)
+    assert np.array_equal(to_u64(q[torch.from_numpy(pos.astype(np.int64)).to(DEV)]), qs)
+    ref = O.query_u64(oracle_of(built), qs, O.REMAP_CLEF)
+    got = to_u64(out[torch.from_numpy(pos.astype(np.int64)).to(DEV)])
+    assert np.array_equal(got, ref)
+
+    say("[fullsize] u64 non-members, tuned and plain kernels")
+    nm = K.nonmember_keys(RANDOM, seed=31)
+    got_nm = to_u64(mphf.query(torch.from_numpy(nm.view(np.int64)).to(DEV)))
+    assert np.array_equal(got_nm, O.query_u64(oracle_of(built), nm, O.REMAP_CLEF))
+
+    mphf.set_kernel(P.KERNEL_PLAIN, 1, 256)
+    mphf.set_occupancy(0)
+    out2 = torch.empty_like(out)
+    mphf.query_into(q, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+
+
+def test_bytes_3e8_default():
+    n = 3 * 10**8
+    say(f"[fullsize] strings n={n}: device strings + library build")
+    d_data, d_off = P.gen_strings(n, K.KEY_SEED)
+    data = d_data.cpu().numpy()
+    offsets = d_off.cpu().numpy().view(np.uint64)
+    del d_data, d_off
+    built = P.build_bytes(data, offsets, index_bits=32, threads=threads())
+    del data, offsets
+    check_params(built.params, n)
+    mphf = P.Mphf.from_built(built)
+    qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    tuned(mphf, lambda: mphf.query_bytes_into(qd, qo, out), n, P.KEY_BYTES)
+    mphf.query_bytes_into(qd, qo, out)
+    torch.cuda.synchronize()
+    say("[fullsize] strings bijection")
+    assert bijective(out, n)
+
+    say("[fullsize] strings sampled oracle parity")
+    pos = sample_positions(n, 12)
+    sd, so = K.string_query_stream_at(n, pos)
+    ref = O.query_bytes(oracle_of(built), sd, so, O.REMAP_CLEF)
+    got = to_u64(out[torch.from_numpy(pos.astype(np.int64)).to(DEV)])
+    assert np.array_equal(got, ref)
+
+    say("[fullsize] strings: plain kernel agrees")
+    mphf.set_kernel(P.KERNEL_PLAIN, 1, 256)
+    mphf.set_occupancy(0)
+    out2 = torch.empty_like(out)
+    mphf.query_bytes_into(qd, qo, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)

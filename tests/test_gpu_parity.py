@@ -269,7 +269,8 @@ def test_device_front_half_build_equals_oracle(n):
     keys = K.u64_keys(n, seed=321)
     say(f"[build-device] n={n}")
     kt = torch.from_numpy(keys.view(np.int64)).to(DEV)
-    b = P.build_u64_device(kt, threads=8)
+    b = P.build_u64_device(kt, threads=8, placement="host")
+    assert b.placement == "host"
     m = O.build_u64(keys)
     assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
     assert b.params.seed == m.params.seed
@@ -279,7 +280,7 @@ def test_device_front_half_rejects_duplicates():
     keys = K.u64_keys(5000, seed=3)
     keys[4000] = keys[12]
     with pytest.raises(P.PtrHashError) as e:
-        P.build_u64_device(torch.from_numpy(keys.view(np.int64)).to(DEV))
+        P.build_u64_device(torch.from_numpy(keys.view(np.int64)).to(DEV), placement="host")
     assert e.value.code == P.E_DUPLICATE
 
 
