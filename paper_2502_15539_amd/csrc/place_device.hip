@@ -238,33 +238,43 @@ __device__ uint64_t heap_pop(LdsState &st) {
     return top;
 }
 
-// A 64-entry window of a read-only u64 stream held one entry per lane, with
-// the next window already in flight.
+// Wait for every vector memory operation of this wavefront (s_waitcnt with
+// vmcnt = 0, expcnt and lgkmcnt left at their maxima). Placed where a load's
+// result must be complete on that path only, so that the compiler's own wait
+// is not put on the paths that merge after it.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A window of a read-only u64 stream held one entry per lane in two
+// registers (entries [start, start + 128)). It is refilled synchronously:
+// a prefetched register would be read by the loop's phi copies on every
+// iteration, and the wait for it would also wait for every store in flight.
 struct Window {
     const uint64_t *base;
-    uint64_t len, start;  // entries [start, start + 64) are in cur
-    uint64_t cur, next;
+    uint64_t len, start;
+    uint64_t w0, w1;
 
-    __device__ void load(uint64_t at, uint64_t &dst) const {
-        const uint64_t i = at + (uint64_t)__lane_id();
-        dst = i < len ? base[i] : 0;
-    }
-    __device__ void reset(uint64_t at) {
+    __device__ void fill(uint64_t at) {
         start = at;
-        load(at, cur);
-        load(at + kWave, next);
+        const uint64_t i = at + (uint64_t)__lane_id();
+        w0 = i < len ? base[i] : 0;
+        w1 = i + kWave < len ? base[i + kWave] : 0;
+        wait_vm();
     }
-    // bring entry `at` into cur (at >= start)
-    __device__ void seek(uint64_t at) {
-        if (at >= start + 2 * kWave) {
-            reset(at);
-        } else if (at >= start + kWave) {
-            cur = next;
-            start += kWave;
-            load(start + kWave, next);
-        }
+    // entries [at, at + 64) available: at - start <= 64
+    __device__ void need(uint64_t at) {
+        if (at > start + kWave) fill(at);
     }
-    __device__ uint64_t get(uint64_t at) const { return bcast64(cur, (int)(at - start)); }
+    // entry at (wave-uniform), at - start < 128
+    __device__ uint64_t get(uint64_t at) const {
+        const uint32_t o = (uint32_t)(at - start);
+        return o < (uint32_t)kWave ? bcast64(w0, (int)o) : bcast64(w1, (int)(o - kWave));
+    }
+    // entry at + lane for lane < 64, at - start <= 64
+    __device__ uint64_t lanes(uint64_t at) const {
+        const uint32_t o = (uint32_t)(at - start) + (uint32_t)__lane_id();
+        const uint64_t x0 = shfl64(w0, (int)(o & 63)), x1 = shfl64(w1, (int)(o & 63));
+        return o < (uint32_t)kWave ? x0 : x1;
+    }
 };
 
 // One wavefront per workgroup; a persistent grid takes parts from a counter.
@@ -294,12 +304,9 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
         const uint64_t kend = gb0 + B;
         uint64_t c = a.bst[gb0];             // its first hash in OH
         Window ow{a.okeys, kend, 0, 0, 0};
-        ow.reset(k);
-        // hashes: 128 entries [hw.start, hw.start + 128) in two windows
-        Window hw{a.OH, a.n, 0, 0, 0};
-        hw.reset(c);
-        uint64_t hw2 = 0;
-        hw.load(c + 2 * kWave, hw2);
+        ow.fill(k);
+        Window hw{a.OH, a.n, 0, 0, 0};  // hashes in search order
+        hw.fill(c);
         uint64_t placed = 0, ev = 0;
         uint32_t status = kPlaceOk;
         const uint64_t max_iter = (uint64_t)B + a.max_evictions + 2;
@@ -310,7 +317,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             uint32_t s = 0, id = 0;
             bool from_order = false;
             if (k < kend) {
-                ow.seek(k);
+                ow.need(k);
                 decode_key(ow.get(k), a.max_size, a.size_bits, a.id_bits, s, id);
                 from_order = s > 0;
             }
@@ -331,40 +338,34 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             if (from_order) {
                 src = a.OH + c;
                 if (small) {
-                    if (c >= hw.start + kWave) {
-                        if (c >= hw.start + 2 * kWave) {
-                            hw.reset(c);
-                            hw.load(c + 2 * kWave, hw2);
-                        } else {
-                            hw.cur = hw.next;
-                            hw.next = hw2;
-                            hw.start += kWave;
-                            hw.load(hw.start + 2 * kWave, hw2);
-                        }
-                    }
-                    const uint32_t o = (uint32_t)(c - hw.start) + (uint32_t)lane;  // < 128
-                    const uint64_t x0 = shfl64(hw.cur, (int)(o & 63)), x1 = shfl64(hw.next, (int)(o & 63));
-                    h0 = o < (uint32_t)kWave ? x0 : x1;
+                    hw.need(c);
+                    h0 = hw.lanes(c);
                 }
                 c += s;
                 ++k;
             } else {
                 src = a.H + a.bst[gb0 + id];
                 if (small && (uint32_t)lane < s) h0 = src[lane];
+                wait_vm();
             }
             if (!small && s > kMaxBucket) { status = kPlaceTooLarge; break; }
 
             int chosen = -1;
             // 1) smallest pilot with free, distinct slots
             if (small) {
+                uint32_t myq = 0;
                 for (int round = 0; round < 4 && chosen < 0; ++round) {
                     const uint32_t pl = (uint32_t)(round * kWave + lane);
                     const uint64_t hp = pilot_hash(m, pl);
                     bool free = true;
-                    for (uint32_t j = 0; j < s; ++j) {
-                        const uint64_t hj = bcast64(h0, (int)j);
-                        if (free && is_taken(bits, local_slot(m, hj, hp))) free = false;
-                        if ((j & 3) == 3 && __ballot(free) == 0) break;
+                    // four independent LDS reads per step, then one test
+                    for (uint32_t j = 0; j < s; j += 4) {
+                        bool t = is_taken(bits, local_slot(m, bcast64(h0, (int)j), hp));
+                        if (j + 1 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 1), hp));
+                        if (j + 2 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 2), hp));
+                        if (j + 3 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 3), hp));
+                        free = free && !t;
+                        if (__ballot(free) == 0) break;
                     }
                     uint64_t cand = __ballot(free);
                     while (cand) {
@@ -373,7 +374,6 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         const uint32_t pc = (uint32_t)(round * kWave + lbit);
                         // tentative: set the bits; a key that finds its bit already
                         // set collides with a sibling (all slots were free)
-                        uint32_t myq = 0;
                         bool mine = false, dup = false;
                         if ((uint32_t)lane < s) {
                             myq = local_slot(m, h0, pilot_hash(m, pc));
@@ -384,6 +384,14 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         if (mine) atomicAnd(&bits[myq >> 5], ~(1u << (myq & 31)));
                         __builtin_amdgcn_wave_barrier();
                     }
+                }
+                if (chosen >= 0) {
+                    // placed without evictions: one record store per key, no waits
+                    ++placed;
+                    const SlotRec rec{id, (uint32_t)placed, s, (uint32_t)chosen};
+                    if ((uint32_t)lane < s) recs[myq] = rec;
+                    if (lane == 0) a.pilots[gb0 + id] = (uint8_t)chosen;
+                    continue;
                 }
             } else {
                 for (uint32_t pc = 0; pc < 256 && chosen < 0; ++pc) {

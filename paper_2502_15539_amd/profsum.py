@@ -33,6 +33,7 @@ def kernel_source_hash() -> str:
 
 
 def short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     return re.sub(r"\(.*", "", name).replace("void ", "")
 
 
