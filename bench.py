@@ -146,7 +146,8 @@ def profiled_traffic(workload, ms, n):
     if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
         return None, {"stale_profile": path}
     b = t["traffic_bytes_per_launch"]
-    return b, {"traffic_GBps": b / (ms / 1e3) / 1e9, "traffic_bytes_per_key": b / n,
+    return b, {"traffic_GBps": b / (ms / 1e3) / 1e9, "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+               "traffic_bytes_per_key": b / n,
                "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": path}
 
 

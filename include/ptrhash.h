@@ -354,6 +354,12 @@ PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const u
  * threads (a multiple of 256); sink receives one u32 sum per lane. */
 PTRHASH_API int ptrhash_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,
                                           uint32_t lanes, hipStream_t stream);
+/* line-size probe: as the pure gather, and each random offset o also reads
+ * the byte at o ^ xor_dist (32: same 64-byte half, 64: other half of the
+ * same 128-byte line, 128: the next line). table_len a positive multiple of
+ * 256; xor_dist 32, 64 or 128, else E_INVAL. */
+PTRHASH_API int ptrhash_bench_gather_pair(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,
+                                          uint32_t lanes, uint32_t xor_dist, hipStream_t stream);
 PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane,
                                    int block, hipStream_t stream);
 

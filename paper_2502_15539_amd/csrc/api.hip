@@ -534,6 +534,17 @@ PTRHASH_API int ptrhash_bench_gather_pure(uint64_t n, const uint8_t *table, uint
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "pure gather launch");
 }
 
+PTRHASH_API int ptrhash_bench_gather_pair(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,
+                                          uint32_t lanes, uint32_t xor_dist, hipStream_t stream) {
+    if (n == 0) return PTRHASH_OK;
+    if (!table || !sink || table_len < 256 || table_len % 256)
+        return fail(PTRHASH_E_INVAL, "NULL table/sink, or table_len not a positive multiple of 256");
+    if (lanes < 256 || lanes % 256) return fail(PTRHASH_E_INVAL, "lanes must be a positive multiple of 256");
+    if (xor_dist != 32 && xor_dist != 64 && xor_dist != 128) return fail(PTRHASH_E_INVAL, "xor_dist: 32, 64 or 128");
+    const hipError_t e = launch_bench_gather_pair(n, table, table_len, xor_dist, sink, lanes / 256, stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "pair gather launch");
+}
+
 PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane, int block,
                                    hipStream_t stream) {
     if (!valid_tuning(kKernelPipelined, keys_per_lane, block)) return fail(PTRHASH_E_INVAL, "bad tuning");

@@ -62,6 +62,8 @@ hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t 
                                uint64_t *out, int keys_per_lane, int block, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T, uint32_t *sink, uint32_t grid,
                                     hipStream_t s);
+hipError_t launch_bench_gather_pair(uint64_t n, const uint8_t *table, uint64_t T, uint32_t D, uint32_t *sink,
+                                    uint32_t grid, hipStream_t s);
 hipError_t launch_bench_copy(const uint64_t *keys, uint64_t nq, uint64_t *out, int keys_per_lane, int block,
                              hipStream_t s);
 

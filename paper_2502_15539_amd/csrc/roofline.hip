@@ -76,7 +76,35 @@ __global__ void __launch_bounds__(256) bench_gather_pure_k(uint64_t n, const uin
     sink[t] = acc;
 }
 
+// Line-size probe: as the pure gather, plus a second byte at o xor D for
+// each random offset o (D = 32: same 64-byte half, 64: other half of the
+// same 128-byte line, 128: the neighbouring line). T is a multiple of 256,
+// so o xor D < T.
+__global__ void __launch_bounds__(256) bench_gather_pair_k(uint64_t n, const uint8_t *__restrict__ table,
+                                                           uint64_t T, uint32_t D, uint32_t *__restrict__ sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (uint64_t i = t; i < n; i += 4 * stride) {
+        uint32_t b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t k = i + j * stride;
+            const uint64_t o = __umul64hi(sm_mix(k), T);
+            b[j] = k < n ? table[o] + table[o ^ D] : 0;
+        }
+        acc += b[0] + b[1] + b[2] + b[3];
+    }
+    sink[t] = acc;
+}
+
 static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+hipError_t launch_bench_gather_pair(uint64_t n, const uint8_t *table, uint64_t T, uint32_t D, uint32_t *sink,
+                                    uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(bench_gather_pair_k, dim3(grid), dim3(256), 0, s, n, table, T, D, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t T, uint32_t *sink, uint32_t grid,
                                     hipStream_t s) {

@@ -121,6 +121,8 @@ _SIGS = {
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
                                        C.c_int, C.c_void_p]),
+    "ptrhash_bench_gather_pair": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
+                                            C.c_uint32, C.c_void_p]),
     "ptrhash_bench_gather_pure": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
                                             C.c_void_p]),
     "ptrhash_bench_copy": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
@@ -353,6 +355,12 @@ def bench_gather_pure(n, table, sink, stream=None):
     """sink: int32 cuda tensor, its length (a multiple of 256) = lanes."""
     _check(lib().ptrhash_bench_gather_pure(int(n), _dev_ptr(table), table.numel(), _dev_ptr(sink), sink.numel(),
                                            _stream(stream)), "ptrhash_bench_gather_pure")
+
+
+def bench_gather_pair(n, table, sink, xor_dist, stream=None):
+    """Pure gather plus a second byte at o ^ xor_dist of each random offset o."""
+    _check(lib().ptrhash_bench_gather_pair(int(n), _dev_ptr(table), table.numel(), _dev_ptr(sink), sink.numel(),
+                                           int(xor_dist), _stream(stream)), "ptrhash_bench_gather_pair")
 
 
 def bench_copy(keys, out, keys_per_lane=4, block=256, stream=None):

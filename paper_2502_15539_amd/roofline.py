@@ -1,11 +1,17 @@
 """Random-gather roofline of the device, as a function of table size.
 
     python -m paper_2502_15539_amd.roofline [--n 1e9]
+    python -m paper_2502_15539_amd.roofline --lines [--n 2.68e8]
 
 For each table size T (from L2-resident to far beyond the MALL) it times,
 on n keys: the streaming gather (u64 key in, one random byte of T, u64 out;
 the memory pattern of a query), the pure gather (random bytes only, no
 streams) and, once, the stream copy (16 B per key). Prints one JSON object.
+
+--lines times, for a few table sizes, the pure gather alone and with a
+second byte read at o xor D of every random offset o (D = 32, 64, 128): a
+second byte in the same 128-byte line costs nothing if a miss fills the
+whole line, and a second miss if it does not.
 """
 from __future__ import annotations
 
@@ -24,7 +30,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--reps", type=int, default=4)
+    ap.add_argument("--lines", action="store_true", help="line-size probe instead of the size sweep")
     args = ap.parse_args()
+    if args.lines:
+        return lines(args)
     n = int(args.n)
     keys = torch.empty(n, dtype=torch.int64, device="cuda")
     P.gen_u64_keys(keys, 1)
@@ -52,6 +61,36 @@ def main():
                               "pure_gather_ms": pure, "pure_G_per_s": n / pure / 1e6})
         print(f"T={T / 2**20:8.1f} MiB  gather {g:7.3f} ms ({n / g / 1e6:6.1f} G/s)  "
               f"pure {pure:7.3f} ms ({n / pure / 1e6:6.1f} G/s)", flush=True)
+        del table
+    print(json.dumps(res), flush=True)
+
+
+def lines(args):
+    import torch
+
+    n = int(args.n) if args.n != 1e9 else 1 << 28
+    sink = torch.empty(256 * 4096, dtype=torch.int32, device="cuda")
+
+    def t(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.reps
+
+    res = {"n": n, "tables": []}
+    for T in (64 << 20, 1 << 30, 4 << 30):
+        table = torch.randint(0, 256, (T,), dtype=torch.uint8, device="cuda")
+        row = {"table_bytes": T, "single_ms": t(lambda: P.bench_gather_pure(n, table, sink))}
+        for d in (32, 64, 128):
+            row[f"pair_xor{d}_ms"] = t(lambda: P.bench_gather_pair(n, table, sink, d))
+        res["tables"].append(row)
+        print(f"T={T >> 20:5d} MiB  single {row['single_ms']:.3f} ms  +o^32 {row['pair_xor32_ms']:.3f}  "
+              f"+o^64 {row['pair_xor64_ms']:.3f}  +o^128 {row['pair_xor128_ms']:.3f} ms", flush=True)
         del table
     print(json.dumps(res), flush=True)
 
