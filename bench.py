@@ -355,7 +355,7 @@ def run_serve(args, torch, K, P):
            "data": "synthetic (seeded SplitMix64 keys, log-uniform sizes, Poisson arrivals)",
            "config": {"workload": WORKLOADS["serve_c5"][3], "requests": args.requests, "parallelism": "single GPU"},
            "serving": res}
-    return rec, res["served_equals_plain"]
+    return rec, res["served_equals_plain"] and res["batched_on_device"]["multi_equals_plain"]
 
 
 def main():

@@ -192,6 +192,22 @@ PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_q
 PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t stream);
 
 /*
+ * Launch shape of a plan's persistent kernel: keys_per_lane (loads in
+ * flight per lane: 1, 2, 4 or 8), block (threads per workgroup, 64..1024,
+ * a multiple of 64) and blocks_per_cu (resident workgroups per compute
+ * unit; 0 = as many as the kernel allows), so that the autotuner can pick
+ * them. A batch is cut into tiles of keys_per_lane * block keys, so the
+ * batches must be set again (ptrhash_multi_plan_set) after a change before
+ * the next launch (E_STATE otherwise); a captured graph keeps the shape it
+ * was captured with. New plans take the process default
+ * (ptrhash_set_multi_kernel; initially 4, 256, 0), which ptrhash_query_multi
+ * also uses. Errors: E_INVAL.
+ */
+PTRHASH_API int ptrhash_multi_plan_set_kernel(ptrhash_multi_plan *plan, int keys_per_lane, int block,
+                                              int blocks_per_cu);
+PTRHASH_API int ptrhash_set_multi_kernel(int keys_per_lane, int block, int blocks_per_cu);
+
+/*
  * Evaluate k batches (descs: host array, copied before return) in one
  * persistent launch on stream, through an internal ring of plans whose
  * reuse waits for the launch that last used the slot. Not for use while
@@ -217,6 +233,9 @@ typedef struct ptrhash_server_config {
     int copy_threads;     /* host threads helping with key/index copies (0..64) */
     int zero_copy;        /* 1: kernels read keys and write indices in mapped host memory;
                              0: keys and indices are copied to/from device arenas */
+    int keys_per_lane;    /* launch shape of the multi-MPHF kernel, as in */
+    int block;            /* ptrhash_multi_plan_set_kernel; keys_per_lane = 0 */
+    int blocks_per_cu;    /* takes the process default for all three */
 } ptrhash_server_config;
 
 typedef struct ptrhash_server_metrics {

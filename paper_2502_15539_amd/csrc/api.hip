@@ -1,6 +1,7 @@
 // C ABI of the query library: handles, parameter rule, validation, device
 // residency of an MPHF and kernel dispatch. All compute happens in the HIP
 // kernels; this layer only checks arguments and launches.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -27,6 +28,7 @@ struct ptrhash_multi_plan {
     MultiTable *d_table = nullptr;  // device copy read by the kernel
     MultiTable *h_stage = nullptr;  // pinned host staging copy
     size_t used_bytes = 0;
+    ptrhash::MultiTuning tuning;
     uint32_t grid = 0;
 };
 
@@ -137,7 +139,7 @@ int check_params(const ptrhash_params *p) {
 }  // namespace
 
 namespace ptrhash {
-int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k) {
+int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile) {
     // validate everything before touching the table
     for (int i = 0; i < k; ++i) {
         const ptrhash_query_desc &d = descs[i];
@@ -168,19 +170,40 @@ int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k) {
         m.out = d.out;
         m.nq = d.n_q;
         m.tile_begin = tiles;
-        tiles += (d.n_q + kMultiTile - 1) / kMultiTile;
+        tiles += (d.n_q + tile - 1) / tile;
     }
     t->count = c;
+    t->tile = tile;
     t->tiles = tiles;
     return PTRHASH_OK;
 }
 
-uint32_t multi_grid() {
+uint32_t multi_grid(const MultiTuning &t) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 1;
-    return (uint32_t)cus * (uint32_t)multi_blocks_per_cu();
+    int per_cu = multi_blocks_per_cu(t);
+    if (t.blocks_per_cu > 0 && t.blocks_per_cu < per_cu) per_cu = t.blocks_per_cu;
+    return (uint32_t)cus * (uint32_t)per_cu;
+}
+
+bool valid_multi_tuning(int keys_per_lane, int block, int blocks_per_cu) {
+    if (keys_per_lane != 1 && keys_per_lane != 2 && keys_per_lane != 4 && keys_per_lane != 8) return false;
+    if (block < 64 || block > 1024 || block % 64) return false;
+    return blocks_per_cu >= 0 && blocks_per_cu <= 64;
+}
+
+namespace {
+std::atomic<int> g_multi_kpl{4}, g_multi_block{256}, g_multi_bpc{0};
+}
+
+MultiTuning multi_default_tuning() {
+    MultiTuning t;
+    t.keys_per_lane = g_multi_kpl.load();
+    t.block = g_multi_block.load();
+    t.blocks_per_cu = g_multi_bpc.load();
+    return t;
 }
 
 bool valid_tuning(int kernel, int keys_per_lane, int block) {
@@ -428,7 +451,9 @@ PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **ou
         return fail(PTRHASH_E_NOMEM, "hipHostMalloc for the staging table: %s", hipGetErrorString(e));
     }
     std::memset(p->h_stage, 0, bytes);
-    p->grid = multi_grid();
+    p->tuning = multi_default_tuning();
+    p->h_stage->tile = multi_tile(p->tuning);
+    p->grid = multi_grid(p->tuning);
     p->used_bytes = multi_table_bytes(1);
     *out = p;
     return PTRHASH_OK;
@@ -438,15 +463,40 @@ PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_q
     if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
     if (k < 0 || (k > 0 && !descs)) return fail(PTRHASH_E_INVAL, "bad descriptor array");
     if (k > plan->max) return fail(PTRHASH_E_RANGE, "%d batches exceed the plan's %d", k, plan->max);
-    const int rc = fill_multi_table(plan->h_stage, descs, k);
+    const int rc = fill_multi_table(plan->h_stage, descs, k, multi_tile(plan->tuning));
     if (rc) return rc;
     const uint32_t c = plan->h_stage->count;
     plan->used_bytes = multi_table_bytes(c ? (int)c : 1);
     return PTRHASH_OK;
 }
 
+PTRHASH_API int ptrhash_multi_plan_set_kernel(ptrhash_multi_plan *plan, int keys_per_lane, int block,
+                                              int blocks_per_cu) {
+    if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
+    if (!valid_multi_tuning(keys_per_lane, block, blocks_per_cu))
+        return fail(PTRHASH_E_INVAL, "keys_per_lane in {1, 2, 4, 8}, block 64..1024 (multiple of 64), "
+                                     "blocks_per_cu 0..64");
+    plan->tuning.keys_per_lane = keys_per_lane;
+    plan->tuning.block = block;
+    plan->tuning.blocks_per_cu = blocks_per_cu;
+    plan->grid = multi_grid(plan->tuning);
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_set_multi_kernel(int keys_per_lane, int block, int blocks_per_cu) {
+    if (!valid_multi_tuning(keys_per_lane, block, blocks_per_cu))
+        return fail(PTRHASH_E_INVAL, "keys_per_lane in {1, 2, 4, 8}, block 64..1024 (multiple of 64), "
+                                     "blocks_per_cu 0..64");
+    g_multi_kpl.store(keys_per_lane);
+    g_multi_block.store(block);
+    g_multi_bpc.store(blocks_per_cu);
+    return PTRHASH_OK;
+}
+
 PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t stream) {
     if (!plan) return fail(PTRHASH_E_INVAL, "plan is NULL");
+    if (plan->h_stage->tile != multi_tile(plan->tuning))
+        return fail(PTRHASH_E_STATE, "the kernel changed after ptrhash_multi_plan_set: set the batches again");
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(stream, &cs);
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
@@ -456,7 +506,7 @@ PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t 
     const size_t bytes = capturing ? multi_table_bytes(plan->max) : plan->used_bytes;
     e = hipMemcpyAsync(plan->d_table, plan->h_stage, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "batch table copy");
-    e = launch_query_multi(plan->d_table, plan->grid, stream);
+    e = launch_query_multi(plan->d_table, plan->tuning, plan->grid, stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query_multi launch");
 }
 
@@ -500,9 +550,16 @@ PTRHASH_API int ptrhash_query_multi(const ptrhash_query_desc *descs, int k, hipS
         if ((e = hipEventSynchronize(r.done[slot])) != hipSuccess) return hip_fail(e, "waiting for a plan slot");
         r.pending[slot] = false;
     }
-    int rc = ptrhash_multi_plan_set(r.plans[slot], descs, k);
+    const MultiTuning t = multi_default_tuning();
+    ptrhash_multi_plan *plan = r.plans[slot];
+    if (t.keys_per_lane != plan->tuning.keys_per_lane || t.block != plan->tuning.block ||
+        t.blocks_per_cu != plan->tuning.blocks_per_cu) {
+        int rc = ptrhash_multi_plan_set_kernel(plan, t.keys_per_lane, t.block, t.blocks_per_cu);
+        if (rc) return rc;
+    }
+    int rc = ptrhash_multi_plan_set(plan, descs, k);
     if (rc) return rc;
-    rc = ptrhash_multi_plan_launch(r.plans[slot], stream);
+    rc = ptrhash_multi_plan_launch(plan, stream);
     if (rc) return rc;
     if ((e = hipEventRecord(r.done[slot], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     r.pending[slot] = true;

@@ -20,10 +20,17 @@ struct Tuning {
 
 bool valid_tuning(int kernel, int keys_per_lane, int block);
 
-// Persistent multi-batch launch: tile = kMultiK keys per lane x kMultiBlock lanes.
-constexpr int kMultiK = 4;
-constexpr int kMultiBlock = 256;
-constexpr uint64_t kMultiTile = (uint64_t)kMultiK * kMultiBlock;
+// Persistent multi-batch launch. A tile is keys_per_lane * block keys of one
+// batch; the grid is CUs x resident workgroups per CU (blocks_per_cu, or the
+// most the kernel allows when 0).
+struct MultiTuning {
+    int keys_per_lane = 4;
+    int block = 256;
+    int blocks_per_cu = 0;
+};
+bool valid_multi_tuning(int keys_per_lane, int block, int blocks_per_cu);
+inline uint32_t multi_tile(const MultiTuning &t) { return (uint32_t)t.keys_per_lane * (uint32_t)t.block; }
+MultiTuning multi_default_tuning();  // the process-wide default (ptrhash_set_multi_kernel)
 
 struct MultiDesc {
     DevMphf m;
@@ -38,7 +45,7 @@ struct MultiDesc {
 
 struct MultiTable {
     uint32_t count;           // batches (>= 1)
-    uint32_t pad_;
+    uint32_t tile;            // keys per tile the table was numbered with
     uint64_t tiles;           // total tiles
     MultiDesc descs[1];       // count entries follow
 };
@@ -47,11 +54,13 @@ inline size_t multi_table_bytes(int max_descs) {
     return sizeof(MultiTable) + sizeof(MultiDesc) * (size_t)(max_descs > 1 ? max_descs - 1 : 0);
 }
 
-hipError_t launch_query_multi(const MultiTable *table, uint32_t grid, hipStream_t s);
-int multi_blocks_per_cu();  // resident blocks of query_multi per compute unit
-uint32_t multi_grid();      // persistent grid size of query_multi on the current device
-// Validate k batches and write them (and the tile prefix sums) into t.
-int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k);
+// The table must have been filled with multi_tile(t); grid from multi_grid(t).
+hipError_t launch_query_multi(const MultiTable *table, const MultiTuning &t, uint32_t grid, hipStream_t s);
+int multi_blocks_per_cu(const MultiTuning &t);  // most resident workgroups of the kernel per compute unit
+uint32_t multi_grid(const MultiTuning &t);      // persistent grid size on the current device
+// Validate k batches and write them (and the tile prefix sums for tiles of
+// `tile` keys) into t.
+int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile);
 
 hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
                             const Tuning &t, hipStream_t s);

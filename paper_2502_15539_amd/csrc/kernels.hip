@@ -127,14 +127,18 @@ __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict_
 }
 
 // Persistent launch over a table of query batches (each against its own
-// resident MPHF). Every batch is cut into tiles of kMultiK*blockDim keys;
+// resident MPHF). Every batch is cut into tiles of K*blockDim keys (the
+// table records the tile size it was numbered with);
 // tiles are numbered globally (MultiDesc::tile_begin is a prefix sum) and
 // the grid strides over them, so batches of any mix of sizes share one
 // launch. The header (batch count, tile count) lives in device memory next
 // to the batches, so a captured launch can be replayed over new batches.
-__global__ void __launch_bounds__(kMultiBlock) query_multi(const MultiTable *__restrict__ table) {
+template <int K>
+__global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict__ table) {
     const uint32_t count = table->count;
     const uint64_t tiles = table->tiles;
+    const uint32_t tile = table->tile;
+    if (tile != (uint32_t)K * blockDim.x) return;  // table numbered for another launch shape
     const MultiDesc *__restrict__ d = table->descs;
     for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         // last descriptor whose first tile is <= t (uniform across the block)
@@ -144,21 +148,21 @@ __global__ void __launch_bounds__(kMultiBlock) query_multi(const MultiTable *__r
             if (d[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
         const MultiDesc &q = d[lo];
-        const uint64_t base = (t - q.tile_begin) * (uint64_t)(kMultiK * kMultiBlock) + threadIdx.x;
+        const uint64_t base = (t - q.tile_begin) * (uint64_t)tile + threadIdx.x;
         if (q.bytes) {
             if (q.out64)
-                process_tile<kMultiK, uint64_t, true>(q.m, nullptr, q.data, q.offsets, q.nq,
-                                                      static_cast<uint64_t *>(q.out), base, kMultiBlock);
+                process_tile<K, uint64_t, true>(q.m, nullptr, q.data, q.offsets, q.nq, static_cast<uint64_t *>(q.out),
+                                                base, blockDim.x);
             else
-                process_tile<kMultiK, uint32_t, true>(q.m, nullptr, q.data, q.offsets, q.nq,
-                                                      static_cast<uint32_t *>(q.out), base, kMultiBlock);
+                process_tile<K, uint32_t, true>(q.m, nullptr, q.data, q.offsets, q.nq, static_cast<uint32_t *>(q.out),
+                                                base, blockDim.x);
         } else {
             if (q.out64)
-                process_tile<kMultiK, uint64_t, false>(q.m, q.keys, nullptr, nullptr, q.nq,
-                                                       static_cast<uint64_t *>(q.out), base, kMultiBlock);
+                process_tile<K, uint64_t, false>(q.m, q.keys, nullptr, nullptr, q.nq, static_cast<uint64_t *>(q.out),
+                                                 base, blockDim.x);
             else
-                process_tile<kMultiK, uint32_t, false>(q.m, q.keys, nullptr, nullptr, q.nq,
-                                                       static_cast<uint32_t *>(q.out), base, kMultiBlock);
+                process_tile<K, uint32_t, false>(q.m, q.keys, nullptr, nullptr, q.nq, static_cast<uint32_t *>(q.out),
+                                                 base, blockDim.x);
         }
     }
 }
@@ -232,16 +236,31 @@ hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint6
                  : launch_bytes_t<uint32_t>(m, data, offsets, nq, out, t, s);
 }
 
-int multi_blocks_per_cu() {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, query_multi, kMultiBlock, 0) != hipSuccess || blocks < 1)
-        blocks = 4;
-    return blocks;
+template <typename F>
+static hipError_t with_multi_kernel(int K, F &&f) {
+    switch (K) {
+    case 1: return f(query_multi<1>);
+    case 2: return f(query_multi<2>);
+    case 4: return f(query_multi<4>);
+    case 8: return f(query_multi<8>);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_query_multi(const MultiTable *table, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(query_multi, dim3(grid), dim3(kMultiBlock), 0, s, table);
-    return hipGetLastError();
+int multi_blocks_per_cu(const MultiTuning &t) {
+    int blocks = 0;
+    const hipError_t e = with_multi_kernel(t.keys_per_lane, [&](auto kern) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, t.block, 0);
+    });
+    return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
+hipError_t launch_query_multi(const MultiTable *table, const MultiTuning &t, uint32_t grid, hipStream_t s) {
+    const hipError_t e = with_multi_kernel(t.keys_per_lane, [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3((uint32_t)t.block), 0, s, table);
+        return hipSuccess;
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace ptrhash

@@ -175,6 +175,7 @@ struct ptrhash_server {
     int error = PTRHASH_OK;
     bool stop = false;
     int device = 0;
+    ptrhash::MultiTuning tuning;  // launch shape of the multi-MPHF kernel
     uint32_t grid = 0;
     std::thread worker;
 };
@@ -252,9 +253,9 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
     if (zc) {
         // the kernel reads keys and the batch table from, and writes indices
         // to, mapped coherent host memory: one stream operation per launch
-        rc = ptrhash::fill_multi_table(s.h_table, descs.data(), (int)descs.size());
+        rc = ptrhash::fill_multi_table(s.h_table, descs.data(), (int)descs.size(), ptrhash::multi_tile(srv->tuning));
         if (rc == PTRHASH_OK) {
-            e = ptrhash::launch_query_multi(s.v_table, srv->grid, s.stream);
+            e = ptrhash::launch_query_multi(s.v_table, srv->tuning, srv->grid, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
             if (e != hipSuccess) rc = hip_err(e, "serving launch");
         }
@@ -338,6 +339,9 @@ PTRHASH_API int ptrhash_server_default_config(ptrhash_server_config *cfg) {
     cfg->max_queued_keys = 1ull << 28;
     cfg->copy_threads = 4;
     cfg->zero_copy = 1;
+    cfg->keys_per_lane = 0;  // the process default launch shape
+    cfg->block = 0;
+    cfg->blocks_per_cu = 0;
     return PTRHASH_OK;
 }
 
@@ -352,13 +356,23 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
         return ptrhash::set_error(PTRHASH_E_INVAL, "max_queued_keys must be >= slot_keys");
     if (cfg->copy_threads < 0 || cfg->copy_threads > 64)
         return ptrhash::set_error(PTRHASH_E_INVAL, "copy_threads must be 0..64");
+    ptrhash::MultiTuning tuning = ptrhash::multi_default_tuning();
+    if (cfg->keys_per_lane != 0) {
+        if (!ptrhash::valid_multi_tuning(cfg->keys_per_lane, cfg->block, cfg->blocks_per_cu))
+            return ptrhash::set_error(PTRHASH_E_INVAL, "keys_per_lane in {1, 2, 4, 8}, block 64..1024 "
+                                                       "(multiple of 64), blocks_per_cu 0..64");
+        tuning.keys_per_lane = cfg->keys_per_lane;
+        tuning.block = cfg->block;
+        tuning.blocks_per_cu = cfg->blocks_per_cu;
+    }
     ptrhash_server *srv = new (std::nothrow) ptrhash_server();
     if (!srv) return ptrhash::set_error(PTRHASH_E_NOMEM, "server allocation failed");
     srv->cfg = *cfg;
     hipError_t e = hipGetDevice(&srv->device);
     int rc = e == hipSuccess ? PTRHASH_OK : hip_err(e, "hipGetDevice");
     srv->slots.resize(cfg->streams);
-    srv->grid = ptrhash::multi_grid();
+    srv->tuning = tuning;
+    srv->grid = ptrhash::multi_grid(tuning);
     const bool zc = cfg->zero_copy != 0;
     const unsigned pin = zc ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
     for (Slot &s : srv->slots) {
@@ -388,6 +402,8 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
                 break;
             }
             rc = ptrhash_multi_plan_create(cfg->max_batches, &s.plan);
+            if (rc == PTRHASH_OK)
+                rc = ptrhash_multi_plan_set_kernel(s.plan, tuning.keys_per_lane, tuning.block, tuning.blocks_per_cu);
         }
     }
     if (rc) {

@@ -72,7 +72,8 @@ class QueryDesc(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("streams", C.c_int), ("max_batches", C.c_int), ("slot_keys", C.c_uint64),
-                ("max_queued_keys", C.c_uint64), ("copy_threads", C.c_int), ("zero_copy", C.c_int)]
+                ("max_queued_keys", C.c_uint64), ("copy_threads", C.c_int), ("zero_copy", C.c_int),
+                ("keys_per_lane", C.c_int), ("block", C.c_int), ("blocks_per_cu", C.c_int)]
 
 
 class ServerMetrics(C.Structure):
@@ -121,6 +122,8 @@ _SIGS = {
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
                                        C.c_int, C.c_void_p]),
+    "ptrhash_multi_plan_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "ptrhash_set_multi_kernel": (C.c_int, [C.c_int, C.c_int, C.c_int]),
     "ptrhash_bench_gather_pair": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
                                             C.c_uint32, C.c_void_p]),
     "ptrhash_bench_gather_pure": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
@@ -397,10 +400,22 @@ def make_descs(batches):
     return arr
 
 
+def multi_max() -> int:
+    """Most batches one multi-MPHF launch (plan, server launch, query_multi) takes."""
+    return int(lib().ptrhash_multi_max())
+
+
 def query_multi(batches, stream=None):
     """One persistent launch over all batches (see ptrhash_query_multi)."""
     arr = make_descs(batches)
     _check(lib().ptrhash_query_multi(arr, len(batches), _stream(stream)), "ptrhash_query_multi")
+
+
+def set_multi_kernel(keys_per_lane=4, block=256, blocks_per_cu=0):
+    """Process default launch shape of multi-MPHF launches (new plans and
+    servers, and query_multi)."""
+    _check(lib().ptrhash_set_multi_kernel(int(keys_per_lane), int(block), int(blocks_per_cu)),
+           "ptrhash_set_multi_kernel")
 
 
 class MultiPlan:
@@ -417,6 +432,11 @@ class MultiPlan:
 
     def launch(self, stream=None):
         _check(lib().ptrhash_multi_plan_launch(self._h, _stream(stream)), "ptrhash_multi_plan_launch")
+
+    def set_kernel(self, keys_per_lane=4, block=256, blocks_per_cu=0):
+        """Launch shape (call set() again before the next launch)."""
+        _check(lib().ptrhash_multi_plan_set_kernel(self._h, int(keys_per_lane), int(block), int(blocks_per_cu)),
+               "ptrhash_multi_plan_set_kernel")
 
     def close(self):
         if self._h:
@@ -435,9 +455,13 @@ class Server:
     host indices out); see ptrhash_server_* in include/ptrhash.h."""
 
     def __init__(self, streams=None, max_batches=None, slot_keys=None, max_queued_keys=None, copy_threads=None,
-                 zero_copy=None):
+                 zero_copy=None, multi_kernel=None):
+        """multi_kernel: (keys_per_lane, block, blocks_per_cu) of the
+        multi-MPHF launches, or None for the process default."""
         cfg = ServerConfig()
         _check(lib().ptrhash_server_default_config(C.byref(cfg)), "ptrhash_server_default_config")
+        if multi_kernel is not None:
+            cfg.keys_per_lane, cfg.block, cfg.blocks_per_cu = (int(x) for x in multi_kernel)
         if streams is not None:
             cfg.streams = streams
         if max_batches is not None:

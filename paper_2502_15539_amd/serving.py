@@ -9,6 +9,12 @@ queued at t = 0), then open-loop Poisson arrivals at fractions of it; each
 run reports p50/p99 latency (arrival -> indices delivered) and throughput.
 The comparison is one plain one-key-per-lane launch per request on the same
 GPU (keys copied in, one query, indices copied out, in arrival order).
+
+Before serving, the batched form alone is measured with every request's keys
+already in device memory: one persistent multi-MPHF launch over up to 4096
+requests (launch shape picked by the autotuner, also as a replayed HIP
+graph) against one plain launch per request. The server then uses the
+tuned launch shape.
 """
 from __future__ import annotations
 
@@ -88,14 +94,60 @@ SERVER_CONFIGS = [  # (streams, slot_keys, copy_threads, zero_copy)
 ]
 
 
+def run_batched(torch, reqs, log=print, reps=5):
+    """Device-resident batches: tuned multi-MPHF plan launch (and its graph
+    replay) vs one plain launch per request. Returns (results, shape)."""
+    from . import autotune
+
+    reqs = reqs[:P.multi_max()]
+    keys = sum(len(q) for _, q, _ in reqs)
+    dev = [(m, torch.from_numpy(q.view(np.int64)).to("cuda"), torch.empty(len(q), dtype=torch.int32, device="cuda"))
+           for m, q, _ in reqs]
+    plan = P.MultiPlan(len(dev))
+    shape, sweep = autotune.tune_multi(torch, plan, dev, use_cache=False)
+    torch.cuda.synchronize()
+    t_multi = autotune._time(torch, plan.launch, reps)
+    multi_out = [o.clone() for _, _, o in dev]
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    t_graph = autotune._time(torch, graph.replay, reps)
+
+    def plain_all():
+        for m, q, o in dev:
+            m.query_into(q, o)
+
+    for m, _, _ in dev:
+        m.set_kernel(P.KERNEL_PLAIN, 1, 256)
+    t_plain = autotune._time(torch, plain_all, max(1, reps // 2))
+    for m, _, _ in dev:
+        m.set_kernel(P.KERNEL_PIPELINED, 4, 256)
+    agree = all(torch.equal(a, o) for a, (_, _, o) in zip(multi_out, dev))
+    plan.close()
+    res = {"requests": len(dev), "keys": keys, "multi_shape": {"keys_per_lane": shape[0], "block": shape[1],
+                                                               "blocks_per_cu": shape[2]},
+           "multi_ms": t_multi, "multi_keys_per_s": keys / t_multi * 1e3,
+           "graph_replay_ms": t_graph, "plain_per_request_ms": t_plain, "plain_keys_per_s": keys / t_plain * 1e3,
+           "speedup": t_plain / t_multi, "multi_equals_plain": agree,
+           "shape_sweep_ms": {f"{c[0]}/{c[1]}/{c[2]}": v for c, v in sorted(sweep.items())}}
+    log(f"[serve] batched on device: {len(dev)} requests, {keys} keys: multi launch {t_multi:.3f} ms "
+        f"({keys / t_multi / 1e6:.1f} G keys/s, shape {shape}), graph replay {t_graph:.3f} ms, "
+        f"plain per request {t_plain:.3f} ms ({t_plain / t_multi:.1f}x), agree={agree}")
+    return res, shape
+
+
 def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0, log=print):
     fleet = build_fleet(threads=threads, log=log)
     reqs = make_requests(fleet, n_requests)
+    batched, shape = run_batched(torch, reqs, log=log)
     # pick the server configuration by its saturated rate (everything queued at t = 0)
     tried = {}
     for streams, slot, copiers, zc in SERVER_CONFIGS:
         srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
-                       copy_threads=copiers, zero_copy=zc)
+                       copy_threads=copiers, zero_copy=zc, multi_kernel=shape)
         run_server(srv, reqs[:500], np.zeros(500))
         r = run_server(srv, reqs, np.zeros(len(reqs)))
         # latency at a light open-loop load (25 % of this configuration's saturated rate)
@@ -110,7 +162,7 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
     streams, slot, copiers, zc = best
     sat = tried[best]
     srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
-                   copy_threads=copiers, zero_copy=zc)
+                   copy_threads=copiers, zero_copy=zc, multi_kernel=shape)
     run_server(srv, reqs[:500], np.zeros(500))
     log(f"[serve] saturated: {sat['req_per_s']:.0f} req/s, {sat['keys_per_s'] / 1e9:.2f} G keys/s")
     runs = []
@@ -129,10 +181,11 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
     agree = all(np.array_equal(a, b) for a, b in zip(served[:2000], base_out))
     log(f"[serve] plain per-request baseline: {base['req_per_s']:.0f} req/s p50 {base['p50_us']:.0f}us "
         f"agree={agree}")
-    return {"saturated": sat, "open_loop": runs, "plain_per_request": base, "served_equals_plain": agree,
+    return {"batched_on_device": batched, "saturated": sat, "open_loop": runs, "plain_per_request": base,
+            "served_equals_plain": agree,
             "mphfs": len(fleet), "resident_keys": int(sum(len(k) for k, _ in fleet)),
             "server_config": {"streams": streams, "slot_keys": slot, "copy_threads": copiers, "zero_copy": zc,
-                              "max_batches": 1024},
+                              "max_batches": 1024, "multi_shape": list(shape)},
             "config_sweep": {f"streams={c[0]},slot={c[1]},copiers={c[2]},zero_copy={c[3]}":
                              {"req_per_s": v["req_per_s"], "keys_per_s": v["keys_per_s"],
                               "light_p50_us": v["light_p50_us"], "light_p99_us": v["light_p99_us"]}

@@ -223,3 +223,13 @@ def test_device_build_rejects_bad_arguments_before_any_device_call():
     q = P.params_default(1000, key_kind=P.KEY_BYTES)
     assert f(C.c_void_p(16), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
     assert b"key_kind" in P.lib().ptrhash_last_error()
+
+
+def test_multi_launch_shape_validation_without_device():
+    f = P.lib().ptrhash_set_multi_kernel
+    for bad in [(3, 256, 0), (16, 256, 0), (4, 32, 0), (4, 1088, 0), (4, 100, 0), (4, 256, -1), (4, 256, 65)]:
+        assert f(*bad) == P.E_INVAL, bad
+    assert f(4, 256, 0) == P.OK  # the initial default
+    with pytest.raises(P.PtrHashError) as e:
+        P.Server(multi_kernel=(5, 256, 0))
+    assert e.value.code == P.E_INVAL

@@ -166,3 +166,76 @@ def test_plan_graph_capture_and_replay():
         x = torch.arange(1000, device=DEV).sum()
         assert int(x) == 499500
     plan.close()
+
+
+@pytest.mark.parametrize("kpl,block,bpc", [(1, 64, 0), (2, 128, 2), (4, 256, 0), (8, 512, 1), (1, 1024, 0),
+                                           (8, 64, 8)])
+def test_plan_launch_shapes_match_oracle(kpl, block, bpc):
+    """Every launch shape the autotuner may pick gives the oracle's indices."""
+    items, rng = pool()
+    plan = P.MultiPlan(64)
+    plan.set_kernel(kpl, block, bpc)
+    batches, wants = [], []
+    for s in [0, 1, 5, 63, 64, 65, 1000, 4097, 30_000]:
+        g, q, out, want = make_batch(items[int(rng.integers(len(items)))], rng, s)
+        batches.append((g, q, out))
+        wants.append(want)
+    plan.set(batches)
+    say(f"[multi] shape kpl={kpl} block={block} bpc={bpc}")
+    plan.launch()
+    torch.cuda.synchronize()
+    for (g, q, out), want in zip(batches, wants):
+        assert np.array_equal(host(out, 0), want)
+    plan.close()
+
+
+def test_plan_shape_change_needs_new_set_and_default_applies():
+    items, rng = pool()
+    g, q, out, want = make_batch(items[3], rng, 3000)
+    plan = P.MultiPlan(4)
+    plan.set([(g, q, out)])
+    plan.set_kernel(2, 128, 0)
+    with pytest.raises(P.PtrHashError) as e:
+        plan.launch()
+    assert e.value.code == P.E_STATE
+    with pytest.raises(P.PtrHashError) as e:
+        plan.set_kernel(3, 128, 0)
+    assert e.value.code == P.E_INVAL
+    plan.set([(g, q, out)])
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out, 0), want)
+    plan.close()
+    # the process default reaches query_multi
+    P.set_multi_kernel(8, 128, 2)
+    try:
+        g, q, out, want = make_batch(items[5], rng, 7777)
+        P.query_multi([(g, q, out)])
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out, 0), want)
+    finally:
+        P.set_multi_kernel(4, 256, 0)
+
+
+def test_multi_autotuner(tmp_path, monkeypatch):
+    from paper_2502_15539_amd import autotune
+
+    monkeypatch.setenv("PTRHASH_TUNE_CACHE", str(tmp_path / "tune.json"))
+    items, rng = pool()
+    u64_items = [it for it in items if it[0] == "u64"]
+    bs = [make_batch(u64_items[i % len(u64_items)], rng, int(rng.integers(1, 20_000))) for i in range(24)]
+    batches = [(g, q, o) for g, q, o, _ in bs]
+    plan = P.MultiPlan(64)
+    cands = autotune.multi_candidates(kpls=(1, 4), blocks=(128, 256), occupancy=(0, 2))
+    say(f"[multi] tuning {len(cands)} shapes")
+    best, res = autotune.tune_multi(torch, plan, batches, cands=cands, reps=1)
+    assert best in res and len(res) == len(cands)
+    best2, res2 = autotune.tune_multi(torch, plan, batches, cands=cands, reps=1)
+    assert best2 == best and res2 == {}
+    for _, _, o, _ in bs:
+        o.fill_(-1)
+    plan.launch()
+    torch.cuda.synchronize()
+    for g, q, out, want in bs:
+        assert np.array_equal(host(out, 0), want)
+    plan.close()

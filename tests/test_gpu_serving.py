@@ -53,11 +53,11 @@ def requests(rng, count, max_size):
     return reqs
 
 
-@pytest.mark.parametrize("zero_copy", [1, 0])
-def test_alone_equals_mix_equals_oracle(zero_copy):
+@pytest.mark.parametrize("zero_copy,shape", [(1, None), (0, None), (1, (1, 128, 2)), (0, (8, 512, 0))])
+def test_alone_equals_mix_equals_oracle(zero_copy, shape):
     rng = np.random.default_rng(3)
     reqs = requests(rng, 120, 20_000)
-    srv = P.Server(streams=2, max_batches=64, slot_keys=1 << 16, zero_copy=zero_copy)
+    srv = P.Server(streams=2, max_batches=64, slot_keys=1 << 16, zero_copy=zero_copy, multi_kernel=shape)
     say(f"[serve] alone: {len(reqs)} requests")
     alone = []
     for g, q, out, want in reqs:
@@ -115,3 +115,6 @@ def test_server_errors():
         srv.submit(P.Mphf(), big[:5], out[:5])  # not loaded
     assert e.value.code == P.E_STATE
     srv.close()
+    with pytest.raises(P.PtrHashError) as e:
+        P.Server(streams=1, max_batches=4, slot_keys=100, multi_kernel=(4, 100, 0))
+    assert e.value.code == P.E_INVAL
