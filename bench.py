@@ -226,6 +226,45 @@ def oracle_baseline(args, p, built, q, out, bits, n):
     return cpu
 
 
+def oracle_baseline_bytes(args, p, built, qd, qo, out, n):
+    """As oracle_baseline, for byte-string keys: the first queries of the
+    same shuffled string stream (at most 5*10^7 of them)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+
+    ns = min(args.cpu_sample, n, 50_000_000)
+    offs = qo[:ns + 1].cpu().numpy().view(np.uint64)
+    data = qd[:int(offs[-1]) + 64].cpu().numpy()
+    op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    m = O.Mphf(op, built.pilots, None, built.remap, None)
+
+    def run(lo, hi):
+        o = offs[lo:hi + 1]
+        return O.query_bytes(m, data[int(o[0]):int(o[-1]) + 64], o - o[0], O.REMAP_CLEF)
+
+    one = max(1, ns // 4)
+    c0 = time.perf_counter()
+    run(0, one)
+    single = (time.perf_counter() - c0) / one
+    cores = min(16, os.cpu_count() or 1)
+    bounds = np.linspace(0, ns, cores + 1).astype(np.int64)
+    c0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        parts = list(ex.map(lambda i: run(int(bounds[i]), int(bounds[i + 1])), range(cores)))
+    cdt = time.perf_counter() - c0
+    res = np.concatenate(parts)
+    go = out[:ns].cpu().numpy().view(np.uint32).astype(np.uint64)
+    cpu = {"value": ns / cdt, "unit": "queries/s", "cores": cores, "kind": "oracle", "ns_per_key": cdt / ns * 1e9,
+           "sample": f"first {ns} strings of the same shuffled stream on the same MPHF, the C oracle's plain query "
+                     f"loop on {cores} threads (one slice each)",
+           "single_thread_ns_per_key": single * 1e9, "single_thread_sample": one,
+           "matches_gpu": bool(np.array_equal(res, go))}
+    log(f"[bench] cpu oracle: {cores} threads {cdt / ns * 1e9:.2f} ns/key, one thread {single * 1e9:.1f} ns/key, "
+        f"matches_gpu={cpu['matches_gpu']}")
+    return cpu
+
+
 def run_u64(args, torch, K, P):
     n, _, bits, desc = WORKLOADS[args.workload]
     dev = "cuda"
@@ -303,7 +342,7 @@ def run_u64(args, torch, K, P):
                                                "default_clef_stream": 8.7})
     if args.workload != "u64_1e9":
         rec["metric"] = f"queries/s (ns/key) at n={n:.0e} u64 keys"
-    return rec, bij
+    return rec, bij and (cpu is None or cpu["matches_gpu"])
 
 
 def run_bytes(args, torch, K, P):
@@ -332,15 +371,17 @@ def run_bytes(args, torch, K, P):
     rfrac = remap_fraction(torch, P, p, built.pilots, data=qd, offsets=qo)
     per_key = total_bytes / n + 8 + 4 + 1 + rfrac * 64
     log(f"[bench] query {ms:.3f} ms bijective={bij}")
+    cpu = oracle_baseline_bytes(args, p, built, qd, qo, out, n) if args.cpu_sample else None
     rec = record(args, n, ms, wall, desc,
                  {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
                   "bits_per_key": round(built.bits_per_key, 4), "mean_key_bytes": total_bytes / n},
                  "u64", per_key,
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
+                 cpu_baseline=cpu,
                  parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
                  paper_cpu_context_ns_per_key={"default_clef_loop": 37, "default_clef_stream": 23})
     rec["metric"] = "queries/s (ns/key) at n=3e8 byte-string keys"
-    return rec, bij
+    return rec, bij and (cpu is None or cpu["matches_gpu"])
 
 
 def run_serve(args, torch, K, P):
