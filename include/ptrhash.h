@@ -254,6 +254,8 @@ typedef struct ptrhash_server_request {
     uint64_t n_q;
     void *out;
     double arrival_us;    /* offset from the start of the replay */
+    uint32_t mapped;      /* 1: keys/out in ptrhash_host_alloc memory (as ptrhash_server_submit_mapped) */
+    uint32_t pad_;
 } ptrhash_server_request;
 
 /*
@@ -279,6 +281,20 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
 PTRHASH_API int ptrhash_server_submit(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q,
                                       void *out, uint64_t *ticket);
 PTRHASH_API int ptrhash_server_wait(ptrhash_server *srv, uint64_t ticket, double *latency_us);
+
+/*
+ * Mapped requests: keys and out lie inside memory from ptrhash_host_alloc
+ * (mapped, coherent, pinned host memory), so the multi-MPHF kernel reads
+ * the keys and writes the indices there in place, over PCIe, with no host
+ * copy on either side; otherwise as ptrhash_server_submit (the request
+ * still counts against slot_keys). E_INVAL if a buffer is not inside one
+ * such allocation. ptrhash_host_free releases an allocation; no request
+ * may still use it. Errors of host_alloc: E_INVAL, E_NOMEM, E_HIP.
+ */
+PTRHASH_API int ptrhash_server_submit_mapped(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys,
+                                             uint64_t n_q, void *out, uint64_t *ticket);
+PTRHASH_API int ptrhash_host_alloc(uint64_t bytes, void **out);
+PTRHASH_API int ptrhash_host_free(void *p);
 PTRHASH_API int ptrhash_server_replay(ptrhash_server *srv, const ptrhash_server_request *reqs, uint64_t count,
                                       double *makespan_s);
 PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics *out);

@@ -17,6 +17,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -39,6 +40,9 @@ struct Request {
     uint64_t n_q = 0;
     void *out = nullptr;
     uint32_t out_bytes = 4;   // bytes per index
+    bool mapped = false;      // keys/out in mapped host memory: the kernel uses them in place
+    const uint64_t *v_keys = nullptr;  // their device addresses
+    void *v_out = nullptr;
     Clock::time_point t_submit{};
     Clock::time_point t_launch{};
     uint64_t key_off = 0;     // placement inside the slot arena
@@ -134,6 +138,28 @@ class CopyPool {
     bool stop_ = false;
 };
 
+// Mapped, coherent host allocations handed out by ptrhash_host_alloc, so
+// that a request's buffers (any range inside one allocation) can be turned
+// into device addresses without a runtime call per request.
+struct MappedAlloc {
+    uintptr_t end;
+    uintptr_t dev;
+};
+std::mutex g_mapped_mu;
+std::map<uintptr_t, MappedAlloc> g_mapped;  // host base -> end, device base
+
+// Device address of [p, p + bytes) if it lies inside one mapped allocation.
+bool mapped_view(const void *p, uint64_t bytes, void **dev) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    std::lock_guard<std::mutex> l(g_mapped_mu);
+    auto it = g_mapped.upper_bound(a);
+    if (it == g_mapped.begin()) return false;
+    --it;
+    if (a < it->first || a >= it->second.end || bytes > it->second.end - a) return false;
+    *dev = reinterpret_cast<void *>(it->second.dev + (a - it->first));
+    return true;
+}
+
 // Split a copy into chunks of at most 256 KiB.
 void add_copy(std::vector<CopyPool::Job> &jobs, void *dst, const void *src, size_t bytes) {
     constexpr size_t kChunk = 256 << 10;
@@ -201,7 +227,8 @@ void free_slot(Slot &s) {
 // Retire a finished slot: copy indices to the callers' buffers.
 void retire(ptrhash_server *srv, Slot &s) {
     std::vector<CopyPool::Job> jobs;
-    for (const Request &r : s.reqs) add_copy(jobs, r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
+    for (const Request &r : s.reqs)
+        if (!r.mapped) add_copy(jobs, r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
     srv->pool->run(jobs);
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lock(srv->mu);
@@ -222,14 +249,17 @@ void retire(ptrhash_server *srv, Slot &s) {
 // Admit queued requests into a free slot and launch them. Called with the
 // lock held; releases it around the copies and the launch.
 int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
-    uint64_t used = 0, out_used = 0;
+    uint64_t used = 0, out_used = 0, budget = 0;
     while (!srv->queue.empty() && (int)s.reqs.size() < srv->cfg.max_batches) {
         Request &r = srv->queue.front();
-        if (used + r.n_q > srv->cfg.slot_keys) break;
-        r.key_off = used;
-        r.out_off = out_used;
-        used += r.n_q;
-        out_used += (r.n_q * r.out_bytes + 7) & ~7ull;
+        if (budget + r.n_q > srv->cfg.slot_keys) break;
+        budget += r.n_q;
+        if (!r.mapped) {  // arena space for the copies
+            r.key_off = used;
+            r.out_off = out_used;
+            used += r.n_q;
+            out_used += (r.n_q * r.out_bytes + 7) & ~7ull;
+        }
         srv->queued_keys -= r.n_q;
         s.reqs.push_back(r);
         srv->queue.pop_front();
@@ -242,6 +272,10 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
     std::vector<CopyPool::Job> jobs;
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         const Request &r = s.reqs[i];
+        if (r.mapped) {
+            descs[i] = ptrhash_query_desc{r.handle, r.v_keys, nullptr, nullptr, r.n_q, r.v_out};
+            continue;
+        }
         add_copy(jobs, s.h_keys + r.key_off, r.keys, r.n_q * sizeof(uint64_t));
         uint64_t *k = (zc ? s.v_keys : s.d_keys) + r.key_off;
         uint8_t *o = (zc ? s.v_out : s.d_out) + r.out_off;
@@ -260,9 +294,9 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
             if (e != hipSuccess) rc = hip_err(e, "serving launch");
         }
     } else if ((rc = ptrhash_multi_plan_set(s.plan, descs.data(), (int)descs.size())) == PTRHASH_OK) {
-        e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+        if (used) e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) rc = ptrhash_multi_plan_launch(s.plan, s.stream);
-        if (e == hipSuccess && rc == PTRHASH_OK)
+        if (e == hipSuccess && rc == PTRHASH_OK && out_used)
             e = hipMemcpyAsync(s.h_out, s.d_out, out_used, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess && rc == PTRHASH_OK) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) rc = hip_err(e, "serving launch");
@@ -418,7 +452,7 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
 }
 
 static int submit_at(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, void *out,
-                     uint64_t *ticket, Clock::time_point arrival) {
+                     uint64_t *ticket, Clock::time_point arrival, bool mapped) {
     if (!srv || !h || !ticket || (n_q && (!keys || !out))) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL argument");
     ptrhash_params p;
     int rc = ptrhash_get_params(h, &p);
@@ -433,6 +467,14 @@ static int submit_at(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *key
     r.n_q = n_q;
     r.out = out;
     r.out_bytes = p.index_bits / 8;
+    if (mapped && n_q) {
+        void *vk = nullptr, *vo = nullptr;
+        if (!mapped_view(keys, n_q * sizeof(uint64_t), &vk) || !mapped_view(out, n_q * r.out_bytes, &vo))
+            return ptrhash::set_error(PTRHASH_E_INVAL, "mapped request: keys/out not inside ptrhash_host_alloc memory");
+        r.mapped = true;
+        r.v_keys = static_cast<const uint64_t *>(vk);
+        r.v_out = vo;
+    }
     std::unique_lock<std::mutex> lock(srv->mu);
     if (srv->error) return ptrhash::set_error(srv->error, "server stopped after an error");
     if (srv->stop) return ptrhash::set_error(PTRHASH_E_STATE, "server is stopping");
@@ -461,7 +503,42 @@ extern "C" {
 
 PTRHASH_API int ptrhash_server_submit(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys, uint64_t n_q,
                                       void *out, uint64_t *ticket) {
-    return submit_at(srv, h, keys, n_q, out, ticket, Clock::now());
+    return submit_at(srv, h, keys, n_q, out, ticket, Clock::now(), false);
+}
+
+PTRHASH_API int ptrhash_server_submit_mapped(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *keys,
+                                             uint64_t n_q, void *out, uint64_t *ticket) {
+    return submit_at(srv, h, keys, n_q, out, ticket, Clock::now(), true);
+}
+
+PTRHASH_API int ptrhash_host_alloc(uint64_t bytes, void **out) {
+    if (!out || bytes == 0) return ptrhash::set_error(PTRHASH_E_INVAL, "NULL out or zero bytes");
+    void *h = nullptr, *d = nullptr;
+    hipError_t e = hipHostMalloc(&h, bytes, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) return ptrhash::set_error(PTRHASH_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    if ((e = hipHostGetDevicePointer(&d, h, 0)) != hipSuccess) {
+        (void)hipHostFree(h);
+        return ptrhash::set_error(PTRHASH_E_HIP, "hipHostGetDevicePointer: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> l(g_mapped_mu);
+        g_mapped[reinterpret_cast<uintptr_t>(h)] = {reinterpret_cast<uintptr_t>(h) + bytes,
+                                                    reinterpret_cast<uintptr_t>(d)};
+    }
+    *out = h;
+    return PTRHASH_OK;
+}
+
+PTRHASH_API int ptrhash_host_free(void *p) {
+    if (!p) return PTRHASH_OK;
+    {
+        std::lock_guard<std::mutex> l(g_mapped_mu);
+        auto it = g_mapped.find(reinterpret_cast<uintptr_t>(p));
+        if (it == g_mapped.end()) return ptrhash::set_error(PTRHASH_E_INVAL, "not a ptrhash_host_alloc pointer");
+        g_mapped.erase(it);
+    }
+    const hipError_t e = hipHostFree(p);
+    return e == hipSuccess ? PTRHASH_OK : ptrhash::set_error(PTRHASH_E_HIP, "hipHostFree: %s", hipGetErrorString(e));
 }
 
 PTRHASH_API int ptrhash_server_wait(ptrhash_server *srv, uint64_t ticket, double *latency_us) {
@@ -518,7 +595,8 @@ PTRHASH_API int ptrhash_server_replay(ptrhash_server *srv, const ptrhash_server_
         while (Clock::now() < due) {
         }
         for (;;) {
-            const int rc = submit_at(srv, reqs[i].handle, reqs[i].keys, reqs[i].n_q, reqs[i].out, &tickets[i], due);
+            const int rc = submit_at(srv, reqs[i].handle, reqs[i].keys, reqs[i].n_q, reqs[i].out, &tickets[i], due,
+                                     reqs[i].mapped != 0);
             if (rc == PTRHASH_OK) break;
             if (rc != PTRHASH_E_RANGE || reqs[i].n_q > srv->cfg.slot_keys) return rc;
             std::this_thread::yield();  // queue full: the open loop backs off

@@ -87,7 +87,7 @@ class ServerMetrics(C.Structure):
 
 class ServerRequest(C.Structure):
     _fields_ = [("handle", C.c_void_p), ("keys", C.c_void_p), ("n_q", C.c_uint64), ("out", C.c_void_p),
-                ("arrival_us", C.c_double)]
+                ("arrival_us", C.c_double), ("mapped", C.c_uint32), ("pad_", C.c_uint32)]
 
 
 class BuildInfo(C.Structure):
@@ -122,6 +122,10 @@ _SIGS = {
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
                                        C.c_int, C.c_void_p]),
+    "ptrhash_server_submit_mapped": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                               C.POINTER(C.c_uint64)]),
+    "ptrhash_host_alloc": (C.c_int, [C.c_uint64, C.POINTER(C.c_void_p)]),
+    "ptrhash_host_free": (C.c_int, [C.c_void_p]),
     "ptrhash_multi_plan_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ptrhash_set_multi_kernel": (C.c_int, [C.c_int, C.c_int, C.c_int]),
     "ptrhash_bench_gather_pair": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
@@ -411,6 +415,35 @@ def query_multi(batches, stream=None):
     _check(lib().ptrhash_query_multi(arr, len(batches), _stream(stream)), "ptrhash_query_multi")
 
 
+class HostBuffer:
+    """Mapped, pinned host memory from ptrhash_host_alloc (freed on close or
+    collection); ``array`` is a numpy view of it."""
+
+    def __init__(self, nbytes: int):
+        p = C.c_void_p()
+        _check(lib().ptrhash_host_alloc(int(max(1, nbytes)), C.byref(p)), "ptrhash_host_alloc")
+        self._p = p.value
+        self.nbytes = int(max(1, nbytes))
+        self.array = np.ctypeslib.as_array((C.c_uint8 * self.nbytes).from_address(self._p))
+
+    def view(self, offset: int, count: int, dtype) -> np.ndarray:
+        """count elements of dtype at byte offset (a multiple of the item size)."""
+        dt = np.dtype(dtype)
+        return self.array[offset:offset + count * dt.itemsize].view(dt)
+
+    def close(self):
+        if self._p:
+            self.array = None
+            lib().ptrhash_host_free(C.c_void_p(self._p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def set_multi_kernel(keys_per_lane=4, block=256, blocks_per_cu=0):
     """Process default launch shape of multi-MPHF launches (new plans and
     servers, and query_multi)."""
@@ -493,13 +526,26 @@ class Server:
                                            C.byref(t)), "ptrhash_server_submit")
         return t.value
 
+    def submit_mapped(self, mphf: "Mphf", keys: np.ndarray, out: np.ndarray) -> int:
+        """As submit, with keys and out inside host_empty() memory: the
+        kernel reads and writes them in place (no host copies)."""
+        assert keys.dtype == np.uint64 and keys.flags.c_contiguous and out.flags.c_contiguous
+        want = np.uint64 if mphf.params.index_bits == 64 else np.uint32
+        if out.dtype != want or len(out) < len(keys):
+            raise ValueError(f"out must be {np.dtype(want).name}[{len(keys)}]")
+        t = C.c_uint64()
+        _check(lib().ptrhash_server_submit_mapped(self._h, mphf.handle, _np_ptr(keys), len(keys), _np_ptr(out),
+                                                  C.byref(t)), "ptrhash_server_submit_mapped")
+        return t.value
+
     def wait(self, ticket: int) -> float:
         lat = C.c_double()
         _check(lib().ptrhash_server_wait(self._h, int(ticket), C.byref(lat)), "ptrhash_server_wait")
         return lat.value
 
-    def replay(self, reqs) -> float:
-        """reqs: list of (Mphf, keys ndarray, out ndarray, arrival_us)."""
+    def replay(self, reqs, mapped=False) -> float:
+        """reqs: list of (Mphf, keys ndarray, out ndarray, arrival_us);
+        mapped: the arrays are inside host_empty() memory."""
         arr = (ServerRequest * max(1, len(reqs)))()
         for i, (m, k, o, t) in enumerate(reqs):
             arr[i].handle = m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle
@@ -507,6 +553,7 @@ class Server:
             arr[i].n_q = len(k)
             arr[i].out = o.ctypes.data if o.size else None
             arr[i].arrival_us = float(t)
+            arr[i].mapped = int(bool(mapped))
         span = C.c_double()
         _check(lib().ptrhash_server_replay(self._h, arr, len(reqs), C.byref(span)), "ptrhash_server_replay")
         return span.value

@@ -118,3 +118,47 @@ def test_server_errors():
     with pytest.raises(P.PtrHashError) as e:
         P.Server(streams=1, max_batches=4, slot_keys=100, multi_kernel=(4, 100, 0))
     assert e.value.code == P.E_INVAL
+
+
+@pytest.mark.parametrize("zero_copy", [1, 0])
+def test_mapped_requests_in_place(zero_copy):
+    """Requests whose keys and outputs live in mapped pinned memory are
+    served in place, alone or mixed with copied requests; a plain numpy
+    buffer is refused for the mapped path."""
+    rng = np.random.default_rng(8)
+    reqs = requests(rng, 80, 20_000)
+    total = sum(len(q) * 8 + len(o) * o.itemsize + 16 for _, q, o, _ in reqs)
+    buf = P.HostBuffer(total)
+    mapped = []
+    off = 0
+    for g, q, out, want in reqs:
+        k = buf.view(off, len(q), np.uint64)
+        k[:] = q
+        off += len(q) * 8
+        o = buf.view(off, len(out), out.dtype)
+        o[:] = 0
+        off += (len(out) * out.itemsize + 7) // 8 * 8
+        mapped.append((g, k, o, want))
+    srv = P.Server(streams=2, max_batches=64, slot_keys=1 << 16, zero_copy=zero_copy)
+    say(f"[serve] mapped requests zero_copy={zero_copy}")
+    tickets = []
+    for i, ((g, k, o, _), (_, q, out, _)) in enumerate(zip(mapped, reqs)):
+        tickets.append(srv.submit_mapped(g, k, o) if i % 2 == 0 else srv.submit(g, q, out))
+    for t in tickets:
+        srv.wait(t)
+    for i, ((g, k, o, want), (_, q, out, _)) in enumerate(zip(mapped, reqs)):
+        got = o if i % 2 == 0 else out
+        assert np.array_equal(got.astype(np.uint64), want)
+    # replay with every request mapped
+    for _, _, o, _ in mapped:
+        o[:] = 0
+    span = srv.replay([(g, k, o, 0.0) for g, k, o, _ in mapped], mapped=True)
+    assert span > 0
+    for g, k, o, want in mapped:
+        assert np.array_equal(o.astype(np.uint64), want)
+    with pytest.raises(P.PtrHashError) as e:
+        g, q, out, _ = reqs[1]
+        srv.submit_mapped(g, q, out)
+    assert e.value.code == P.E_INVAL
+    srv.close()
+    buf.close()
