@@ -349,18 +349,19 @@ def run_bytes(args, torch, K, P):
     n, _, bits, desc = WORKLOADS[args.workload]
     threads = args.threads or min(16, os.cpu_count() or 1)
     t0 = time.time()
+    # the key set is generated in HBM and built there (hash, sort and pilot
+    # search on the device)
     d_data, d_off = P.gen_strings(n, K.KEY_SEED)
-    data = d_data.cpu().numpy()
-    offsets = d_off.cpu().numpy().view(np.uint64)
-    del d_data, d_off
+    torch.cuda.synchronize()
     t1 = time.time()
-    built = P.build_bytes(data, offsets, index_bits=bits, threads=threads)
+    built = P.build_bytes_device(d_data, d_off, index_bits=bits, threads=threads)
     t2 = time.time()
-    total_bytes = int(offsets[-1])
-    del data, offsets
+    total_bytes = int(d_off[-1].item())
+    del d_data, d_off
+    torch.cuda.empty_cache()
     p = built.params
-    log(f"[bench] strings {t1 - t0:.1f}s ({total_bytes / n:.1f} B/key) build {t2 - t1:.1f}s P={p.num_parts} "
-        f"bits/key={built.bits_per_key:.3f} seed={p.seed}")
+    log(f"[bench] strings {t1 - t0:.1f}s ({total_bytes / n:.1f} B/key) build {t2 - t1:.1f}s ({built.placement} "
+        f"search) P={p.num_parts} bits/key={built.bits_per_key:.3f} seed={p.seed}")
     mphf = P.Mphf.from_built(built)
     qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -379,6 +380,7 @@ def run_bytes(args, torch, K, P):
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  cpu_baseline=cpu,
                  parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
+                 build_search=built.placement,
                  paper_cpu_context_ns_per_key={"default_clef_loop": 37, "default_clef_stream": 23})
     rec["metric"] = "queries/s (ns/key) at n=3e8 byte-string keys"
     return rec, bij and (cpu is None or cpu["matches_gpu"])

@@ -368,6 +368,20 @@ PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrha
 PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                                       void *remap, ptrhash_build_info *info, hipStream_t stream);
 
+/* As ptrhash_build_u64_gpu for byte strings in device memory: key i =
+ * data[offsets[i] .. offsets[i+1]), data 8-byte aligned with at least 64
+ * readable bytes after the last string (the layout the query takes). The
+ * string hash depends on the seed, so every attempt hashes and sorts again;
+ * equal hashes of distinct strings cause a reseed, equal strings E_DUPLICATE,
+ * like ptrhash_build_bytes (same result, byte for byte). 64-bit string
+ * hashes only (E_RANGE for hash_bits = 128); E_RANGE also when more than 64
+ * pairs of keys share a hash (the host construction examines them all).
+ * Device memory: about 32*n + 33*P*B + P*S/8 bytes plus 16*S bytes per
+ * compute unit. */
+PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+                                        ptrhash_params *params, uint8_t *pilots, void *remap,
+                                        ptrhash_build_info *info, hipStream_t stream);
+
 /* As ptrhash_build_u64 for byte strings data[offsets[i] .. offsets[i+1])
  * (host memory); equal 64-bit hashes of distinct strings cause a reseed. */
 PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,

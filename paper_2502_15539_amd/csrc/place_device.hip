@@ -591,6 +591,295 @@ uint32_t bit_width(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) :
 
 constexpr int kMaxSeeds = 16;
 constexpr uint64_t kEvictionFactor = 10;
+constexpr uint32_t kMaxPairs = 64;  // equal-hash pairs of string keys examined per attempt
+
+// String keys: h[i] = the byte-string hash of key i under seed, ids[i] = i.
+__global__ void hash_strings_gpu_k(const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets, uint64_t n,
+                                   uint64_t seed, uint64_t *__restrict__ h, uint64_t *__restrict__ ids) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+        uint64_t unused;
+        h[i] = ptrhash::hash_bytes(seed, data, o0, o1 - o0, false, unused);
+        ids[i] = i;
+    }
+}
+
+// Pairs of keys with equal hashes (adjacent after the sort): count them and
+// keep the first kMaxPairs (ids) for the host to compare.
+__global__ void equal_pairs_k(const uint64_t *__restrict__ H, const uint64_t *__restrict__ ids, uint64_t n,
+                              uint32_t *__restrict__ count, uint64_t *__restrict__ pairs) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        if (H[i] == H[i - 1]) {
+            const uint32_t k = atomicAdd(count, 1u);
+            if (k < kMaxPairs) {
+                pairs[2 * k] = ids[i - 1];
+                pairs[2 * k + 1] = ids[i];
+            }
+        }
+}
+
+// Device pilot search over one set of sorted 64-bit hashes: bucket starts,
+// the (size desc, id asc) order, the hashes in that order, then one search
+// kernel per seed.
+class GpuSearch {
+  public:
+    GpuSearch(const ptrhash_params *params, uint64_t n, hipStream_t stream) : n_(n), stream_(stream) {
+        using namespace ptrhash;
+        mod_ = params->reduce_kind == PTRHASH_REDUCE_MOD;
+        S_ = mod_ ? params->slots : 1ull << params->log2_slots;
+        P_ = params->num_parts;
+        B_ = params->buckets_per_part;
+        total_ = P_ * B_;
+        m_.n = n;
+        m_.parts = (uint32_t)P_;
+        m_.buckets = (uint32_t)B_;
+        m_.log2_slots = mod_ ? 0 : params->log2_slots;
+        m_.gamma = params->gamma;
+        m_.reduce_kind = params->reduce_kind;
+        m_.mod_slots = mod_ ? (uint32_t)S_ : 0;
+        m_.mod_magic = mod_ ? ~0ull / S_ : 0;  // floor((2^64 - 1) / S) = floor(2^64 / S): S is not a power of two
+        timing_ = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
+        tick_ = std::chrono::steady_clock::now();
+    }
+
+    void phase(const char *name) {
+        if (!timing_) return;
+        (void)hipStreamSynchronize(stream_);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[build] %-10s %8.3f s\n", name, std::chrono::duration<double>(now - tick_).count());
+        tick_ = now;
+    }
+
+    // Limits of the device search and the buffers that do not depend on the
+    // hash set.
+    int init() {
+        using namespace ptrhash;
+        words_ = (S_ + 31) / 32;
+        if (P_ > 1 && S_ % 32) return set_error(PTRHASH_E_RANGE, "device placement: S must be a multiple of 32");
+        int dev = 0, cus = 0, lds_max = 0;
+        HIP_OR_FAIL(hipGetDevice(&dev), "device query");
+        HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device query");
+        HIP_OR_FAIL(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device query");
+        lds_ = words_ * sizeof(uint32_t);
+        if (lds_ + sizeof(LdsState) > (size_t)lds_max)
+            return set_error(PTRHASH_E_RANGE, "device placement: %llu slots per part exceed the LDS of one CU",
+                             (unsigned long long)S_);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&place_k),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_);
+        int per_cu = 0;
+        HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k, kWave, lds_), "occupancy query");
+        if (per_cu < 1) return set_error(PTRHASH_E_RANGE, "device placement does not fit one CU");
+        grid_ = std::min<uint64_t>(P_, (uint64_t)cus * (uint64_t)per_cu);
+        taken_words_ = (P_ * S_ + 63) / 64 * 2;  // u32 words, whole u64 words
+        HIP_OR_FAIL(buf_.get(&bst_, total_ + 1), "bucket starts");
+        HIP_OR_FAIL(buf_.get(&maxes_, 2), "device scalars");
+        HIP_OR_FAIL(buf_.get(&flags_, 1), "device scalars");
+        HIP_OR_FAIL(buf_.get(&ka_, total_), "order keys");
+        HIP_OR_FAIL(buf_.get(&kb_, total_), "order keys");
+        HIP_OR_FAIL(buf_.get(&ostart_, total_), "order offsets");
+        HIP_OR_FAIL(buf_.get(&pil_, total_), "pilots");
+        HIP_OR_FAIL(buf_.get(&taken_, taken_words_), "taken bits");
+        HIP_OR_FAIL(buf_.get(&recs_, grid_ * S_), "slot records");
+        HIP_OR_FAIL(buf_.get(&big_, grid_ * (uint64_t)kMaxBucket), "bucket scratch");
+        HIP_OR_FAIL(buf_.get(&next_, 1), "work counter");
+        HIP_OR_FAIL(buf_.get(&status_, P_), "part status");
+        HIP_OR_FAIL(buf_.get(&ev_, P_), "part evictions");
+        return PTRHASH_OK;
+    }
+
+    // Radix-sort n keys (with values if vals) in place through a second
+    // buffer; returns the sorted keys (and values) via the double buffers.
+    int sort(hipcub::DoubleBuffer<uint64_t> &keys, hipcub::DoubleBuffer<uint64_t> *vals) {
+        size_t temp = 0;
+        if (vals)
+            HIP_OR_FAIL(hipcub::DeviceRadixSort::SortPairs(nullptr, temp, keys, *vals, (size_t)n_, 0, 64, stream_),
+                        "sort sizing");
+        else
+            HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, keys, (size_t)n_, 0, 64, stream_),
+                        "sort sizing");
+        if (temp > sort_temp_bytes_) {
+            HIP_OR_FAIL(buf_.get(&sort_temp_, temp), "sort scratch");
+            sort_temp_bytes_ = temp;
+        }
+        if (vals)
+            HIP_OR_FAIL(hipcub::DeviceRadixSort::SortPairs(sort_temp_, temp, keys, *vals, (size_t)n_, 0, 64, stream_),
+                        "sort");
+        else
+            HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(sort_temp_, temp, keys, (size_t)n_, 0, 64, stream_), "sort");
+        return PTRHASH_OK;
+    }
+
+    // Bucket starts, order and ordered hashes for the sorted hashes H (OH: n
+    // entries of scratch). *dup: two equal hashes; *overflow: a part with
+    // more than S keys (then nothing else is prepared).
+    int prepare(const uint64_t *H, uint64_t *OH, bool *dup, bool *overflow) {
+        using namespace ptrhash;
+        H_ = H;
+        OH_ = OH;
+        HIP_OR_FAIL(hipMemsetAsync(flags_, 0, sizeof(uint32_t), stream_), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(maxes_, 0, 2 * sizeof(unsigned long long), stream_), "memset");
+        hipLaunchKernelGGL(bucket_starts_k, dim3(8192), dim3(256), 0, stream_, H, n_, m_, bst_, flags_);
+        HIP_OR_FAIL(hipGetLastError(), "bucket starts launch");
+        hipLaunchKernelGGL(size_max_k, dim3(4096), dim3(256), 0, stream_, bst_, m_, maxes_);
+        HIP_OR_FAIL(hipGetLastError(), "size launch");
+        uint32_t d = 0;
+        unsigned long long mx[2] = {0, 0};
+        HIP_OR_FAIL(hipMemcpyAsync(&d, flags_, sizeof d, hipMemcpyDeviceToHost, stream_), "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(mx, maxes_, sizeof mx, hipMemcpyDeviceToHost, stream_), "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(stream_), "sync");
+        *dup = d != 0;
+        *overflow = mx[1] > S_;
+        if (*dup || *overflow) return PTRHASH_OK;
+        max_size_ = mx[0];
+        if (max_size_ > kMaxBucket)
+            return set_error(PTRHASH_E_RANGE, "device placement: a bucket of %llu keys (at most %u)",
+                             (unsigned long long)max_size_, kMaxBucket);
+        size_bits_ = bit_width(max_size_);
+        id_bits_ = bit_width(B_ - 1);
+        const uint32_t part_bits = bit_width(P_ - 1);
+        if (size_bits_ + id_bits_ + part_bits > 64)
+            return set_error(PTRHASH_E_RANGE, "device placement: sort key width");
+        phase("starts");
+        hipLaunchKernelGGL(order_keys_k, dim3(8192), dim3(256), 0, stream_, bst_, m_, max_size_, size_bits_, id_bits_,
+                           ka_);
+        HIP_OR_FAIL(hipGetLastError(), "order launch");
+        hipcub::DoubleBuffer<uint64_t> kdb(ka_, kb_);
+        const int end_bit = (int)(size_bits_ + id_bits_ + part_bits);
+        size_t temp = 0;
+        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, kdb, (size_t)total_, 0, end_bit, stream_),
+                    "order sort sizing");
+        if (temp > sort_temp_bytes_) {
+            HIP_OR_FAIL(buf_.get(&sort_temp_, temp), "order sort scratch");
+            sort_temp_bytes_ = temp;
+        }
+        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(sort_temp_, temp, kdb, (size_t)total_, 0, end_bit, stream_),
+                    "order sort");
+        okeys_ = kdb.Current();
+        uint64_t *osize = kdb.Alternate();
+        hipLaunchKernelGGL(ordered_sizes_k, dim3(8192), dim3(256), 0, stream_, okeys_, total_, max_size_, size_bits_,
+                           id_bits_, osize);
+        HIP_OR_FAIL(hipGetLastError(), "sizes launch");
+        temp = 0;
+        HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(nullptr, temp, osize, ostart_, (int64_t)total_, stream_),
+                    "scan sizing");
+        if (temp > sort_temp_bytes_) {
+            HIP_OR_FAIL(buf_.get(&sort_temp_, temp), "scan scratch");
+            sort_temp_bytes_ = temp;
+        }
+        HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(sort_temp_, temp, osize, ostart_, (int64_t)total_, stream_),
+                    "scan");
+        hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream_, okeys_, ostart_, bst_, H, m_,
+                           max_size_, size_bits_, id_bits_, OH);
+        HIP_OR_FAIL(hipGetLastError(), "scatter launch");
+        phase("order");
+        return PTRHASH_OK;
+    }
+
+    // One search with the given seed; *failed: some part failed (reseed).
+    int search(uint64_t seed, bool *failed) {
+        using namespace ptrhash;
+        m_.seed = seed;
+        HIP_OR_FAIL(hipMemsetAsync(pil_, 0, total_, stream_), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(taken_, 0, taken_words_ * sizeof(uint32_t), stream_), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(next_, 0, sizeof(uint32_t), stream_), "memset");
+        PlaceArgs a{};
+        a.m = m_;
+        a.H = H_;
+        a.bst = bst_;
+        a.okeys = okeys_;
+        a.OH = OH_;
+        a.n = n_;
+        a.max_size = max_size_;
+        a.size_bits = size_bits_;
+        a.id_bits = id_bits_;
+        a.max_evictions = kEvictionFactor * S_;
+        a.pilots = pil_;
+        a.taken = taken_;
+        a.recs = recs_;
+        a.big = big_;
+        a.next_part = next_;
+        a.status = status_;
+        a.evictions = ev_;
+        hipLaunchKernelGGL(place_k, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
+        HIP_OR_FAIL(hipGetLastError(), "search launch");
+        status_h_.resize(P_);
+        ev_h_.resize(P_);
+        HIP_OR_FAIL(hipMemcpyAsync(status_h_.data(), status_, P_ * sizeof(uint32_t), hipMemcpyDeviceToHost, stream_),
+                    "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(ev_h_.data(), ev_, P_ * sizeof(uint64_t), hipMemcpyDeviceToHost, stream_),
+                    "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(stream_), "search");
+        *failed = false;
+        for (uint64_t p = 0; p < P_; ++p) {
+            if (status_h_[p] == kPlaceHeapFull || status_h_[p] == kPlaceTooLarge)
+                return set_error(PTRHASH_E_RANGE, "device placement: part %llu outside the search's limits (%u)",
+                                 (unsigned long long)p, status_h_[p]);
+            if (status_h_[p] > kPlaceTooLarge)
+                return set_error(PTRHASH_E_HIP, "device placement: inconsistent slot record in part %llu",
+                                 (unsigned long long)p);
+            *failed |= status_h_[p] != kPlaceOk;
+        }
+        phase("search");
+        return PTRHASH_OK;
+    }
+
+    // After a successful search: pilots and remap to the host, statistics.
+    int finish(ptrhash_params *params, uint64_t seed, uint8_t *pilots, void *remap, ptrhash_build_info *info,
+               uint64_t attempts) {
+        using namespace ptrhash;
+        ptrhash_build_info local{};
+        local.attempts = attempts;
+        local.max_bucket_size = max_size_;
+        for (uint64_t p = 0; p < P_; ++p) {
+            local.evictions += ev_h_[p];
+            local.max_part_evictions = std::max(local.max_part_evictions, ev_h_[p]);
+        }
+        std::vector<uint64_t> taken;
+        try {
+            taken.resize(taken_words_ / 2);
+        } catch (const std::bad_alloc &) {
+            return set_error(PTRHASH_E_NOMEM, "host taken-slot bitvector");
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(pilots, pil_, total_, hipMemcpyDeviceToHost, stream_), "pilots to host");
+        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), taken_, taken_words_ * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   stream_),
+                    "taken bits to host");
+        HIP_OR_FAIL(hipStreamSynchronize(stream_), "copy out");
+        ptrhash_params out = *params;
+        out.seed = seed;
+        if (int rc = remap_from_taken(&out, taken, remap)) return rc;
+        phase("remap");
+        params->seed = seed;
+        if (info) *info = local;
+        return PTRHASH_OK;
+    }
+
+    DevBufs &buffers() { return buf_; }
+
+  private:
+    DevBufs buf_;
+    uint64_t n_;
+    hipStream_t stream_;
+    bool mod_ = false, timing_ = false;
+    std::chrono::steady_clock::time_point tick_;
+    uint64_t S_ = 0, P_ = 0, B_ = 0, total_ = 0, words_ = 0, grid_ = 0, taken_words_ = 0;
+    size_t lds_ = 0, sort_temp_bytes_ = 0;
+    ptrhash::DevMphf m_{};
+    uint64_t *bst_ = nullptr, *ka_ = nullptr, *kb_ = nullptr, *ostart_ = nullptr;
+    unsigned long long *maxes_ = nullptr;
+    uint32_t *flags_ = nullptr;
+    uint8_t *sort_temp_ = nullptr;
+    uint8_t *pil_ = nullptr;
+    uint32_t *taken_ = nullptr, *big_ = nullptr, *next_ = nullptr, *status_ = nullptr;
+    ptrhash::SlotRec *recs_ = nullptr;
+    uint64_t *ev_ = nullptr;
+    const uint64_t *H_ = nullptr, *okeys_ = nullptr;
+    uint64_t *OH_ = nullptr;
+    uint64_t max_size_ = 0;
+    uint32_t size_bits_ = 0, id_bits_ = 0;
+    std::vector<uint32_t> status_h_;
+    std::vector<uint64_t> ev_h_;
+};
 
 int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
               ptrhash_build_info *info, hipStream_t stream) {
@@ -598,212 +887,114 @@ int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t 
     if (!keys || !params || !pilots) return set_error(PTRHASH_E_INVAL, "NULL argument");
     if (int rc = check_build_params(n, params, PTRHASH_KEY_U64)) return rc;
     if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
-    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
-    const uint64_t S = mod ? params->slots : 1ull << params->log2_slots;
-    const uint64_t P = params->num_parts, B = params->buckets_per_part, total = P * B;
-    const uint64_t words = (S + 31) / 32;
-    if (P > 1 && S % 32) return set_error(PTRHASH_E_RANGE, "device placement: S must be a multiple of 32");
-
-    int dev = 0, cus = 0, lds_max = 0;
-    HIP_OR_FAIL(hipGetDevice(&dev), "device query");
-    HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device query");
-    HIP_OR_FAIL(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device query");
-    const size_t lds = words * sizeof(uint32_t);
-    if (lds + sizeof(LdsState) > (size_t)lds_max)
-        return set_error(PTRHASH_E_RANGE, "device placement: %llu slots per part exceed the LDS of one CU",
-                         (unsigned long long)S);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&place_k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    int per_cu = 0;
-    HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k, kWave, lds), "occupancy query");
-    if (per_cu < 1) return set_error(PTRHASH_E_RANGE, "device placement does not fit one CU");
-    const uint64_t grid = std::min<uint64_t>(P, (uint64_t)cus * (uint64_t)per_cu);
-
-    const bool timing = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
-    auto tick = std::chrono::steady_clock::now();
-    auto phase = [&](const char *name) {
-        if (!timing) return;
-        (void)hipStreamSynchronize(stream);
-        const auto now = std::chrono::steady_clock::now();
-        std::fprintf(stderr, "[build] %-10s %8.3f s\n", name, std::chrono::duration<double>(now - tick).count());
-        tick = now;
-    };
-
-    DevMphf m{};
-    m.n = n;
-    m.parts = (uint32_t)P;
-    m.buckets = (uint32_t)B;
-    m.log2_slots = mod ? 0 : params->log2_slots;
-    m.gamma = params->gamma;
-    m.reduce_kind = params->reduce_kind;
-    m.mod_slots = mod ? (uint32_t)S : 0;
-    m.mod_magic = mod ? ~0ull / S : 0;  // floor((2^64 - 1) / S) = floor(2^64 / S): S is not a power of two
-
-    DevBufs buf;
-    uint64_t *ha = nullptr, *hb = nullptr, *bst = nullptr, *ka = nullptr, *kb = nullptr, *ostart = nullptr;
-    unsigned long long *maxes = nullptr;
-    uint32_t *flags = nullptr;
-    HIP_OR_FAIL(buf.get(&ha, n), "device hashes");
-    HIP_OR_FAIL(buf.get(&hb, n), "device hashes");
-    HIP_OR_FAIL(buf.get(&bst, total + 1), "bucket starts");
-    HIP_OR_FAIL(buf.get(&maxes, 2), "device scalars");
-    HIP_OR_FAIL(buf.get(&flags, 1), "device scalars");
-
-    // hash and sort
+    GpuSearch g(params, n, stream);
+    if (int rc = g.init()) return rc;
+    uint64_t *ha = nullptr, *hb = nullptr;
+    HIP_OR_FAIL(g.buffers().get(&ha, n), "device hashes");
+    HIP_OR_FAIL(g.buffers().get(&hb, n), "device hashes");
+    // the hash of a u64 key has no seed: hash, sort and order once
     hipLaunchKernelGGL(hash_keys_gpu_k, dim3(8192), dim3(256), 0, stream, keys, n, ha);
     HIP_OR_FAIL(hipGetLastError(), "hash launch");
     hipcub::DoubleBuffer<uint64_t> hdb(ha, hb);
-    size_t temp = 0;
-    HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, hdb, (size_t)n, 0, 64, stream), "sort sizing");
-    {
-        uint8_t *scratch = nullptr;
-        HIP_OR_FAIL(buf.get(&scratch, temp), "sort scratch");
-        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(scratch, temp, hdb, (size_t)n, 0, 64, stream), "sort");
-    }
-    const uint64_t *H = hdb.Current();
-    uint64_t *OH = hdb.Alternate();
-    phase("hash+sort");
-
-    // bucket starts, duplicates, largest bucket and part
-    HIP_OR_FAIL(hipMemsetAsync(flags, 0, sizeof(uint32_t), stream), "memset");
-    HIP_OR_FAIL(hipMemsetAsync(maxes, 0, 2 * sizeof(unsigned long long), stream), "memset");
-    hipLaunchKernelGGL(bucket_starts_k, dim3(8192), dim3(256), 0, stream, H, n, m, bst, flags);
-    HIP_OR_FAIL(hipGetLastError(), "bucket starts launch");
-    hipLaunchKernelGGL(size_max_k, dim3(4096), dim3(256), 0, stream, bst, m, maxes);
-    HIP_OR_FAIL(hipGetLastError(), "size launch");
-    uint32_t dup = 0;
-    unsigned long long mx[2] = {0, 0};
-    HIP_OR_FAIL(hipMemcpyAsync(&dup, flags, sizeof dup, hipMemcpyDeviceToHost, stream), "copy out");
-    HIP_OR_FAIL(hipMemcpyAsync(mx, maxes, sizeof mx, hipMemcpyDeviceToHost, stream), "copy out");
-    HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+    if (int rc = g.sort(hdb, nullptr)) return rc;
+    g.phase("hash+sort");
+    bool dup = false, overflow = false;
+    if (int rc = g.prepare(hdb.Current(), hdb.Alternate(), &dup, &overflow)) return rc;
     if (dup) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
-    if (mx[1] > S) return set_error(PTRHASH_E_BUILD, "a part holds more than S keys");
-    const uint64_t max_size = mx[0];
-    if (max_size > kMaxBucket)
-        return set_error(PTRHASH_E_RANGE, "device placement: a bucket of %llu keys (at most %u)",
-                         (unsigned long long)max_size, kMaxBucket);
-    const uint32_t size_bits = bit_width(max_size), id_bits = bit_width(B - 1), part_bits = bit_width(P - 1);
-    if (size_bits + id_bits + part_bits > 64) return set_error(PTRHASH_E_RANGE, "device placement: sort key width");
-    phase("starts");
-
-    // search order: per part, size descending, then bucket id
-    HIP_OR_FAIL(buf.get(&ka, total), "order keys");
-    HIP_OR_FAIL(buf.get(&kb, total), "order keys");
-    HIP_OR_FAIL(buf.get(&ostart, total), "order offsets");
-    hipLaunchKernelGGL(order_keys_k, dim3(8192), dim3(256), 0, stream, bst, m, max_size, size_bits, id_bits, ka);
-    HIP_OR_FAIL(hipGetLastError(), "order launch");
-    hipcub::DoubleBuffer<uint64_t> kdb(ka, kb);
-    const int end_bit = (int)(size_bits + id_bits + part_bits);
-    temp = 0;
-    HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(nullptr, temp, kdb, (size_t)total, 0, end_bit, stream),
-                "order sort sizing");
-    {
-        uint8_t *scratch = nullptr;
-        HIP_OR_FAIL(buf.get(&scratch, temp), "order sort scratch");
-        HIP_OR_FAIL(hipcub::DeviceRadixSort::SortKeys(scratch, temp, kdb, (size_t)total, 0, end_bit, stream),
-                    "order sort");
-    }
-    const uint64_t *okeys = kdb.Current();
-    uint64_t *osize = kdb.Alternate();
-    hipLaunchKernelGGL(ordered_sizes_k, dim3(8192), dim3(256), 0, stream, okeys, total, max_size, size_bits, id_bits,
-                       osize);
-    HIP_OR_FAIL(hipGetLastError(), "sizes launch");
-    temp = 0;
-    HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(nullptr, temp, osize, ostart, (int64_t)total, stream), "scan sizing");
-    {
-        uint8_t *scratch = nullptr;
-        HIP_OR_FAIL(buf.get(&scratch, temp), "scan scratch");
-        HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(scratch, temp, osize, ostart, (int64_t)total, stream), "scan");
-    }
-    hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream, okeys, ostart, bst, H, m, max_size,
-                       size_bits, id_bits, OH);
-    HIP_OR_FAIL(hipGetLastError(), "scatter launch");
-    phase("order");
-
-    // the search, reseeding failed builds
-    uint8_t *dpil = nullptr;
-    uint32_t *dtaken = nullptr, *dbig = nullptr, *dnext = nullptr, *dstatus = nullptr;
-    SlotRec *drecs = nullptr;
-    uint64_t *dev_ev = nullptr;
-    const uint64_t taken_words = (P * S + 63) / 64 * 2;  // u32 words, whole u64 words
-    HIP_OR_FAIL(buf.get(&dpil, total), "pilots");
-    HIP_OR_FAIL(buf.get(&dtaken, taken_words), "taken bits");
-    HIP_OR_FAIL(buf.get(&drecs, grid * S), "slot records");
-    HIP_OR_FAIL(buf.get(&dbig, grid * (uint64_t)kMaxBucket), "bucket scratch");
-    HIP_OR_FAIL(buf.get(&dnext, 1), "work counter");
-    HIP_OR_FAIL(buf.get(&dstatus, P), "part status");
-    HIP_OR_FAIL(buf.get(&dev_ev, P), "part evictions");
-    std::vector<uint32_t> status(P);
-    std::vector<uint64_t> evs(P);
-    ptrhash_build_info local{};
-    local.max_bucket_size = max_size;
+    if (overflow) return set_error(PTRHASH_E_BUILD, "a part holds more than S keys");
     for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
-        local.attempts = (uint64_t)attempt + 1;
-        m.seed = params->seed + (uint64_t)attempt;
-        HIP_OR_FAIL(hipMemsetAsync(dpil, 0, total, stream), "memset");
-        HIP_OR_FAIL(hipMemsetAsync(dtaken, 0, taken_words * sizeof(uint32_t), stream), "memset");
-        HIP_OR_FAIL(hipMemsetAsync(dnext, 0, sizeof(uint32_t), stream), "memset");
-        PlaceArgs a{};
-        a.m = m;
-        a.H = H;
-        a.bst = bst;
-        a.okeys = okeys;
-        a.OH = OH;
-        a.n = n;
-        a.max_size = max_size;
-        a.size_bits = size_bits;
-        a.id_bits = id_bits;
-        a.max_evictions = kEvictionFactor * S;
-        a.pilots = dpil;
-        a.taken = dtaken;
-        a.recs = drecs;
-        a.big = dbig;
-        a.next_part = dnext;
-        a.status = dstatus;
-        a.evictions = dev_ev;
-        hipLaunchKernelGGL(place_k, dim3((uint32_t)grid), dim3(kWave), lds, stream, a);
-        HIP_OR_FAIL(hipGetLastError(), "search launch");
-        HIP_OR_FAIL(hipMemcpyAsync(status.data(), dstatus, P * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
-                    "copy out");
-        HIP_OR_FAIL(hipMemcpyAsync(evs.data(), dev_ev, P * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-                    "copy out");
-        HIP_OR_FAIL(hipStreamSynchronize(stream), "search");
+        const uint64_t seed = params->seed + (uint64_t)attempt;
         bool failed = false;
-        for (uint64_t p = 0; p < P; ++p) {
-            if (status[p] == kPlaceHeapFull || status[p] == kPlaceTooLarge)
-                return set_error(PTRHASH_E_RANGE, "device placement: part %llu outside the search's limits (%u)",
-                                 (unsigned long long)p, status[p]);
-            if (status[p] > kPlaceTooLarge)
-                return set_error(PTRHASH_E_HIP, "device placement: inconsistent slot record in part %llu",
-                                 (unsigned long long)p);
-            failed |= status[p] != kPlaceOk;
-        }
-        phase("search");
-        if (failed) continue;
-        local.evictions = local.max_part_evictions = 0;
-        for (uint64_t p = 0; p < P; ++p) {
-            local.evictions += evs[p];
-            local.max_part_evictions = std::max(local.max_part_evictions, evs[p]);
-        }
-        std::vector<uint64_t> taken;
-        try {
-            taken.resize(taken_words / 2);
-        } catch (const std::bad_alloc &) {
-            return set_error(PTRHASH_E_NOMEM, "host taken-slot bitvector");
-        }
-        HIP_OR_FAIL(hipMemcpyAsync(pilots, dpil, total, hipMemcpyDeviceToHost, stream), "pilots to host");
-        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), dtaken, taken_words * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
-                    "taken bits to host");
-        HIP_OR_FAIL(hipStreamSynchronize(stream), "copy out");
-        ptrhash_params out = *params;
-        out.seed = m.seed;
-        if (int rc = remap_from_taken(&out, taken, remap)) return rc;
-        phase("remap");
-        params->seed = m.seed;
-        if (info) *info = local;
-        return PTRHASH_OK;
+        if (int rc = g.search(seed, &failed)) return rc;
+        if (!failed) return g.finish(params, seed, pilots, remap, info, (uint64_t)attempt + 1);
     }
-    if (info) *info = local;
+    if (info) *info = ptrhash_build_info{(uint64_t)kMaxSeeds, 0, 0, 0};
+    return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
+}
+
+// Do two of the equal-hash pairs name the same string? (Then the keys are
+// not distinct; otherwise a new seed separates them.)
+int equal_strings(const uint8_t *data, const uint64_t *offsets, const std::vector<uint64_t> &pairs, uint32_t count,
+                  hipStream_t stream, bool *same) {
+    *same = false;
+    for (uint32_t k = 0; k < count && k < kMaxPairs; ++k) {
+        uint64_t o[2][2];
+        for (int j = 0; j < 2; ++j)
+            HIP_OR_FAIL(hipMemcpyAsync(o[j], offsets + pairs[2 * k + j], 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                       stream),
+                        "offsets to host");
+        HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+        const uint64_t la = o[0][1] - o[0][0], lb = o[1][1] - o[1][0];
+        if (la != lb) continue;
+        std::vector<uint8_t> a(la), b(lb);
+        if (la) {
+            HIP_OR_FAIL(hipMemcpyAsync(a.data(), data + o[0][0], la, hipMemcpyDeviceToHost, stream), "key to host");
+            HIP_OR_FAIL(hipMemcpyAsync(b.data(), data + o[1][0], lb, hipMemcpyDeviceToHost, stream), "key to host");
+            HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+        }
+        if (a == b) {
+            *same = true;
+            return PTRHASH_OK;
+        }
+    }
+    return PTRHASH_OK;
+}
+
+int build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n, ptrhash_params *params,
+                    uint8_t *pilots, void *remap, ptrhash_build_info *info, hipStream_t stream) {
+    using namespace ptrhash;
+    if (!data || !offsets || !params || !pilots) return set_error(PTRHASH_E_INVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(data) & 7u) return set_error(PTRHASH_E_INVAL, "data must be 8-byte aligned");
+    if (int rc = check_build_params(n, params, PTRHASH_KEY_BYTES)) return rc;
+    if (params->hash_bits == 128)
+        return set_error(PTRHASH_E_RANGE, "device construction takes 64-bit string hashes (n <= 2^32)");
+    if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
+    GpuSearch g(params, n, stream);
+    if (int rc = g.init()) return rc;
+    uint64_t *ha = nullptr, *hb = nullptr, *ia = nullptr, *ib = nullptr, *pairs = nullptr;
+    uint32_t *npairs = nullptr;
+    HIP_OR_FAIL(g.buffers().get(&ha, n), "device hashes");
+    HIP_OR_FAIL(g.buffers().get(&hb, n), "device hashes");
+    HIP_OR_FAIL(g.buffers().get(&ia, n), "key ids");
+    HIP_OR_FAIL(g.buffers().get(&ib, n), "key ids");
+    HIP_OR_FAIL(g.buffers().get(&pairs, 2 * kMaxPairs), "pairs");
+    HIP_OR_FAIL(g.buffers().get(&npairs, 1), "pairs");
+    std::vector<uint64_t> hpairs(2 * kMaxPairs);
+    for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
+        // the string hash depends on the seed: hash, sort and order per attempt
+        const uint64_t seed = params->seed + (uint64_t)attempt;
+        hipLaunchKernelGGL(hash_strings_gpu_k, dim3(8192), dim3(256), 0, stream, data, offsets, n, seed, ha, ia);
+        HIP_OR_FAIL(hipGetLastError(), "hash launch");
+        hipcub::DoubleBuffer<uint64_t> hdb(ha, hb), idb(ia, ib);
+        if (int rc = g.sort(hdb, &idb)) return rc;
+        g.phase("hash+sort");
+        bool dup = false, overflow = false;
+        // the ids' second buffer serves as the ordered-hash scratch
+        if (int rc = g.prepare(hdb.Current(), idb.Alternate(), &dup, &overflow)) return rc;
+        if (overflow) continue;  // a part with more than S keys: a new seed
+        if (dup) {
+            HIP_OR_FAIL(hipMemsetAsync(npairs, 0, sizeof(uint32_t), stream), "memset");
+            hipLaunchKernelGGL(equal_pairs_k, dim3(4096), dim3(256), 0, stream, hdb.Current(), idb.Current(), n,
+                               npairs, pairs);
+            HIP_OR_FAIL(hipGetLastError(), "pairs launch");
+            uint32_t np = 0;
+            HIP_OR_FAIL(hipMemcpyAsync(&np, npairs, sizeof np, hipMemcpyDeviceToHost, stream), "copy out");
+            HIP_OR_FAIL(hipMemcpyAsync(hpairs.data(), pairs, hpairs.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                       stream),
+                        "copy out");
+            HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+            bool same = false;
+            if (int rc = equal_strings(data, offsets, hpairs, np, stream, &same)) return rc;
+            if (same) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
+            if (np > kMaxPairs)  // more pairs than examined: the host construction checks them all
+                return set_error(PTRHASH_E_RANGE, "device construction: %u equal string hashes", np);
+            continue;  // distinct strings with one hash: a new seed
+        }
+        bool failed = false;
+        if (int rc = g.search(seed, &failed)) return rc;
+        if (!failed) return g.finish(params, seed, pilots, remap, info, (uint64_t)attempt + 1);
+    }
+    if (info) *info = ptrhash_build_info{(uint64_t)kMaxSeeds, 0, 0, 0};
     return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
 }
 
@@ -815,6 +1006,16 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
                                       void *remap, ptrhash_build_info *info, hipStream_t stream) {
     try {
         return build_gpu(keys, n, params, pilots, remap, info, stream);
+    } catch (const std::bad_alloc &) {
+        return ptrhash::set_error(PTRHASH_E_NOMEM, "host allocation failed during construction");
+    }
+}
+
+PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+                                        ptrhash_params *params, uint8_t *pilots, void *remap,
+                                        ptrhash_build_info *info, hipStream_t stream) {
+    try {
+        return build_bytes_gpu(data, offsets, n, params, pilots, remap, info, stream);
     } catch (const std::bad_alloc &) {
         return ptrhash::set_error(PTRHASH_E_NOMEM, "host allocation failed during construction");
     }

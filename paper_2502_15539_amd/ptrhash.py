@@ -118,6 +118,8 @@ _SIGS = {
                                            C.c_int, C.POINTER(BuildInfo), C.c_void_p]),
     "ptrhash_build_u64_gpu": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                         C.POINTER(BuildInfo), C.c_void_p]),
+    "ptrhash_build_bytes_gpu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p,
+                                          C.c_void_p, C.POINTER(BuildInfo), C.c_void_p]),
     "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
@@ -275,6 +277,32 @@ def build_bytes(data: np.ndarray, offsets: np.ndarray, params: Params | None = N
     _check(lib().ptrhash_build_bytes(_np_ptr(data), _np_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
                                      _np_ptr(remap), int(threads), C.byref(info)), "ptrhash_build_bytes")
     return Built(p, pilots, remap, info)
+
+
+def build_bytes_device(data, offsets, params: Params | None = None, threads: int = 0, stream=None,
+                       placement: str = "auto", **kw) -> Built:
+    """Build from byte strings in device memory (a cuda uint8 tensor, 8-byte
+    aligned with 64 readable bytes after the last string, and an int64/uint64
+    offsets tensor of n + 1 entries). placement as in build_u64_device;
+    "host" copies the strings to the host and runs ptrhash_build_bytes."""
+    if placement not in ("auto", "device", "host"):
+        raise ValueError("placement must be 'auto', 'device' or 'host'")
+    n = offsets.numel() - 1
+    p0 = (params if params is not None else params_default(n, key_kind=KEY_BYTES, **kw)).copy()
+    pilots = np.zeros(p0.num_parts * p0.buckets_per_part, dtype=np.uint8)
+    remap = np.zeros(remap_bytes(p0), dtype=np.uint8)
+    info = BuildInfo()
+    if placement != "host":
+        p = p0.copy()
+        rc = lib().ptrhash_build_bytes_gpu(_dev_ptr(data), _dev_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
+                                           _np_ptr(remap), C.byref(info), _stream(stream))
+        if rc == 0:
+            return Built(p, pilots, remap, info, "device")
+        if placement == "device" or rc != E_RANGE:
+            _check(rc, "ptrhash_build_bytes_gpu")
+    b = build_bytes(data.cpu().numpy(), offsets.cpu().numpy().view(np.uint64), params=p0, threads=threads)
+    b.placement = "host"
+    return b
 
 
 class Mphf:

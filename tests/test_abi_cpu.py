@@ -233,3 +233,18 @@ def test_multi_launch_shape_validation_without_device():
     with pytest.raises(P.PtrHashError) as e:
         P.Server(multi_kernel=(5, 256, 0))
     assert e.value.code == P.E_INVAL
+
+
+def test_device_string_build_rejects_bad_arguments_before_any_device_call():
+    import ctypes as C
+
+    p = P.params_default(1000, key_kind=P.KEY_BYTES)
+    pil = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    rm = np.zeros(P.remap_bytes(p), dtype=np.uint8)
+    f = P.lib().ptrhash_build_bytes_gpu
+    assert f(None, C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
+    assert f(C.c_void_p(67), C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None,
+             None) == P.E_INVAL  # unaligned data
+    q = P.params_default(1000)  # u64-key params
+    assert f(C.c_void_p(64), C.c_void_p(64), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None,
+             None) == P.E_INVAL

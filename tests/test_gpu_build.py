@@ -127,3 +127,44 @@ def test_device_search_equals_host_search_1e8():
     assert bd.params.seed == bh.params.seed
     assert bd.info.evictions == bh.info.evictions
     assert np.array_equal(bd.pilots, bh.pilots) and np.array_equal(bd.remap, bh.remap)
+
+
+def dev_strings(data, off):
+    return torch.from_numpy(data).to(DEV), torch.from_numpy(off.view(np.int64)).to(DEV)
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 30_000, 300_000])
+def test_device_string_build_equals_oracle(n):
+    data, off = K.strings(n, seed=61 + n % 13)
+    say(f"[gpu-build] strings n={n}")
+    b = P.build_bytes_device(*dev_strings(data, off), placement="device", index_bits=32)
+    m = O.build_bytes(data, off)
+    same(b, m)
+
+
+def test_device_string_build_errors_and_host_agreement():
+    n = 3_000_000
+    data, off = K.strings(n, seed=9)
+    d, o = dev_strings(data, off)
+    say(f"[gpu-build] strings n={n}: device vs host construction")
+    bd = P.build_bytes_device(d, o, placement="device")
+    bh = P.build_bytes(data, off, threads=min(16, os.cpu_count() or 1))
+    assert bd.params.seed == bh.params.seed
+    assert np.array_equal(bd.pilots, bh.pilots) and np.array_equal(bd.remap, bh.remap)
+    # a repeated string
+    data2, off2 = K.strings(5000, seed=3)
+    lens = np.diff(off2.astype(np.int64))
+    same_len = np.nonzero(lens == lens[10])[0]
+    j = int(same_len[same_len != 10][0])
+    data2[off2[j]:off2[j + 1]] = data2[off2[10]:off2[11]]
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_bytes_device(*dev_strings(data2, off2), placement="device")
+    assert e.value.code == P.E_DUPLICATE
+    # 128-bit string hashes are outside the device construction
+    p = P.params_default(1000, key_kind=P.KEY_BYTES)
+    p.hash_bits = 128
+    d3, o3 = dev_strings(*K.strings(1000, seed=5))
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_bytes_device(d3, o3, params=p, placement="device")
+    assert e.value.code == P.E_RANGE
+    assert P.build_bytes_device(d3, o3, params=p, placement="auto").placement == "host"
