@@ -1,10 +1,11 @@
 """Parity at the full benchmark sizes, in the launch configuration that the
 benchmark times.
 
-At 10^9 u64 keys and 3*10^8 strings the oracle cannot build the MPHF inside
-a test, so the tables come from the library's builder (which the CPU tests
-show to be byte-identical to the oracle's construction at every size the
-oracle can build). The checks here:
+At 10^9 u64 keys, 3*10^8 strings and 4.4*10^9 u64 keys the oracle cannot
+build the MPHF inside a test, so the tables come from the library's device
+construction (which the other tests show to be byte-identical to the
+oracle's construction at every size the oracle can build, and to the
+library's host construction at 10^8 keys). The checks here:
 
 * parameters equal the oracle's parameter rule;
 * the kernel choice is the one the benchmark's autotuner picks, over the same
@@ -18,7 +19,6 @@ oracle can build). The checks here:
   host from the seeded generators, not read back from the device;
 * non-members: 2^20 of them, every output equal to the oracle's.
 """
-import os
 import sys
 
 import numpy as np
@@ -40,10 +40,6 @@ RANDOM = 1 << 20
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def threads():
-    return min(16, os.cpu_count() or 1)
 
 
 def sample_positions(n, seed):
@@ -86,9 +82,9 @@ def tuned(mphf, run, n_q, key_kind):
 
 def test_u64_1e9_default():
     n = 10**9
-    say(f"[fullsize] u64 n={n}: device keys + library build")
+    say(f"[fullsize] u64 n={n}: device keys + device construction")
     keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
-    built = P.build_u64_device(keys, index_bits=64, threads=threads())
+    built = P.build_u64_device(keys, index_bits=64, placement="device")
     del keys
     torch.cuda.empty_cache()
     check_params(built.params, n)
@@ -124,13 +120,11 @@ def test_u64_1e9_default():
 
 def test_bytes_3e8_default():
     n = 3 * 10**8
-    say(f"[fullsize] strings n={n}: device strings + library build")
+    say(f"[fullsize] strings n={n}: device strings + device construction")
     d_data, d_off = P.gen_strings(n, K.KEY_SEED)
-    data = d_data.cpu().numpy()
-    offsets = d_off.cpu().numpy().view(np.uint64)
+    built = P.build_bytes_device(d_data, d_off, index_bits=32, placement="device")
     del d_data, d_off
-    built = P.build_bytes(data, offsets, index_bits=32, threads=threads())
-    del data, offsets
+    torch.cuda.empty_cache()
     check_params(built.params, n)
     mphf = P.Mphf.from_built(built)
     qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
@@ -155,3 +149,40 @@ def test_bytes_3e8_default():
     mphf.query_bytes_into(qd, qo, out2)
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
+
+
+def test_u64_beyond_2_32_keys():
+    """4.4e9 keys: slots, indices and remap values beyond 2^32, 4239 parts.
+    Device construction, the 64-bit query, bijection, sampled oracle parity."""
+    n = 4_400_000_000
+    free, _ = torch.cuda.mem_get_info()
+    if free < 200 * 2**30:
+        pytest.skip(f"needs ~200 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    say(f"[fullsize] u64 n={n}: device keys + device construction")
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
+    built = P.build_u64_device(keys, index_bits=64, placement="device")
+    check_params(built.params, n)
+    assert built.params.num_parts * (1 << built.params.log2_slots) > 2**32
+    torch.cuda.empty_cache()
+    mphf = P.Mphf.from_built(built)
+    q = P.gen_query_stream(keys, n, K.KEY_SEED, K.ORDER_SEED)  # the key buffer is free again
+    out = torch.empty(n, dtype=torch.int64, device=DEV)
+    mphf.query_into(q, out)
+    torch.cuda.synchronize()
+    say("[fullsize] >2^32 bijection")
+    assert int(out.min()) >= 0 and int(out.max()) == n - 1
+    seen = torch.zeros(n, dtype=torch.bool, device=DEV)
+    step = 1 << 30
+    for lo in range(0, n, step):
+        seen[out[lo:lo + step]] = True
+    assert bool(seen.all())
+    del seen
+    say("[fullsize] >2^32 sampled oracle parity")
+    pos = sample_positions(n, 13)
+    qs = K.query_stream_at(n, pos)
+    idx = torch.from_numpy(pos.astype(np.int64)).to(DEV)
+    assert np.array_equal(to_u64(q[idx]), qs)
+    got = to_u64(out[idx])
+    ref = O.query_u64(oracle_of(built), qs, O.REMAP_CLEF)
+    assert np.array_equal(got, ref)
+    assert int(ref.max()) >= 2**32  # the sample reaches indices beyond 32 bits
