@@ -5,11 +5,12 @@
     python -m paper_2502_15539_amd.profsum counters DB [DB ...]
         mean value of each collected counter per kernel (markdown)
     python -m paper_2502_15539_amd.profsum traffic --fetch DB --write DB \\
-            --kernel SUBSTR --copy SUBSTR --copy-bytes N --out JSON
+            --kernel SUBSTR (--copy SUBSTR --copy-bytes N | --scale-from JSON) --out JSON
         HBM bytes per launch of a kernel from FETCH_SIZE and WRITE_SIZE, each
         scaled by the factor that maps the same counter of a plain copy
-        kernel (reading and writing N bytes) onto N; the JSON records a hash
-        of the kernel sources so that a later change voids it.
+        kernel (reading and writing N bytes) onto N, or by the factors of an
+        earlier traffic JSON of the same device; the JSON records a hash of
+        the kernel sources so that a later change voids it.
 """
 from __future__ import annotations
 
@@ -69,11 +70,17 @@ def _mean(db, kernel_sub, counter):
 
 
 def traffic(args) -> dict:
-    copy_fetch = _mean(args.fetch, args.copy, "FETCH_SIZE") * 1024.0
-    copy_write = _mean(args.write, args.copy, "WRITE_SIZE") * 1024.0
+    if args.scale_from:
+        ref = json.load(open(args.scale_from))
+        fs, ws = ref["fetch_scale"], ref["write_scale"]
+    else:
+        if not args.copy or not args.copy_bytes:
+            raise SystemExit("traffic needs --copy and --copy-bytes, or --scale-from")
+        copy_fetch = _mean(args.fetch, args.copy, "FETCH_SIZE") * 1024.0
+        copy_write = _mean(args.write, args.copy, "WRITE_SIZE") * 1024.0
+        fs, ws = args.copy_bytes / copy_fetch, args.copy_bytes / copy_write
     k_fetch = _mean(args.fetch, args.kernel, "FETCH_SIZE") * 1024.0
     k_write = _mean(args.write, args.kernel, "WRITE_SIZE") * 1024.0
-    fs, ws = args.copy_bytes / copy_fetch, args.copy_bytes / copy_write
     res = {"kernel": args.kernel, "fetch_bytes_raw": k_fetch, "write_bytes_raw": k_write,
            "fetch_scale": fs, "write_scale": ws, "fetch_bytes": k_fetch * fs, "write_bytes": k_write * ws,
            "traffic_bytes_per_launch": k_fetch * fs + k_write * ws, "kernel_source_sha256": kernel_source_hash()}
@@ -93,8 +100,9 @@ def main():
     r.add_argument("--fetch", required=True)
     r.add_argument("--write", required=True)
     r.add_argument("--kernel", required=True)
-    r.add_argument("--copy", required=True)
-    r.add_argument("--copy-bytes", type=float, required=True)
+    r.add_argument("--copy")
+    r.add_argument("--copy-bytes", type=float)
+    r.add_argument("--scale-from", help="take the scale factors of this traffic JSON")
     r.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
