@@ -28,8 +28,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kRecent = 16;
 constexpr uint32_t kHeapCap = 1024;       // requeued buckets waiting at once
-constexpr int kMaxRegs = 32;              // bucket keys held per lane: sizes up to 64 * 32
-constexpr uint32_t kMaxBucket = kWave * kMaxRegs;
+constexpr uint32_t kMaxBucket = 2048;     // largest bucket searched (its slots fit the per-wave scratch)
 
 // Slot record written when a bucket is placed: owner bucket (local id), its
 // placement number, its size and its pilot.
