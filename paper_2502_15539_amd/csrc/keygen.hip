@@ -66,24 +66,24 @@ __global__ void gen_query_k(uint64_t key_seed, Feistel f, uint64_t start, uint64
 // with r = SplitMix64(seed, i) and r_j = SplitMix64(seed ^ kByteSalt, 64 i + j).
 constexpr uint64_t kByteSalt = 0x2545F4914F6CDD1Dull;
 
-__device__ inline uint64_t string_of(uint64_t n, bool shuffled, const Feistel &f, uint64_t i) {
+__device__ inline uint64_t string_of(bool shuffled, const Feistel &f, uint64_t i) {
     return shuffled ? permute(f, i) : i;
 }
 
-__global__ void gen_str_len_k(uint64_t n, uint64_t seed, Feistel f, int shuffled, uint64_t start, uint64_t count,
+__global__ void gen_str_len_k(uint64_t seed, Feistel f, int shuffled, uint64_t start, uint64_t count,
                               uint64_t *lengths) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t s = string_of(n, shuffled, f, start + i);
+        const uint64_t s = string_of(shuffled, f, start + i);
         lengths[i] = 10 + splitmix64(seed, s) % 41;
     }
 }
 
-__global__ void gen_str_bytes_k(uint64_t n, uint64_t seed, Feistel f, int shuffled, uint64_t start, uint64_t count,
+__global__ void gen_str_bytes_k(uint64_t seed, Feistel f, int shuffled, uint64_t start, uint64_t count,
                                 const uint64_t *offsets, uint8_t *data) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t s = string_of(n, shuffled, f, start + i);
+        const uint64_t s = string_of(shuffled, f, start + i);
         const uint64_t len = offsets[i + 1] - offsets[i];
         uint8_t *dst = data + offsets[i];
         for (uint64_t j = 0; j < len; ++j)
@@ -134,7 +134,7 @@ PTRHASH_API int ptrhash_gen_string_lengths(uint64_t n, uint64_t seed, uint64_t o
     if (count == 0) return PTRHASH_OK;
     if (!lengths || n == 0 || start > n || count > n - start)
         return ptrhash::set_error(PTRHASH_E_INVAL, "bad string range");
-    hipLaunchKernelGGL(gen_str_len_k, dim3(8192), dim3(256), 0, stream, n, seed, make_feistel(n, order_seed),
+    hipLaunchKernelGGL(gen_str_len_k, dim3(8192), dim3(256), 0, stream, seed, make_feistel(n, order_seed),
                        shuffled, start, count, lengths);
     return launch_err(hipGetLastError(), "gen_string_lengths launch");
 }
@@ -145,7 +145,7 @@ PTRHASH_API int ptrhash_gen_string_bytes(uint64_t n, uint64_t seed, uint64_t ord
     if (count == 0) return PTRHASH_OK;
     if (!offsets || !data || n == 0 || start > n || count > n - start)
         return ptrhash::set_error(PTRHASH_E_INVAL, "bad string range");
-    hipLaunchKernelGGL(gen_str_bytes_k, dim3(8192), dim3(256), 0, stream, n, seed, make_feistel(n, order_seed),
+    hipLaunchKernelGGL(gen_str_bytes_k, dim3(8192), dim3(256), 0, stream, seed, make_feistel(n, order_seed),
                        shuffled, start, count, offsets, data);
     return launch_err(hipGetLastError(), "gen_string_bytes launch");
 }

@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_2502_15539_amd import keygen as K
 from paper_2502_15539_amd import ptrhash as P
 
-from .mphf_pairs import ORACLE_REMAP, lib_params
+from .mphf_pairs import ORACLE_REMAP
 
 cases = st.tuples(
     st.integers(min_value=1, max_value=60_000),       # n
