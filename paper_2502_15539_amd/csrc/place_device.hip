@@ -29,6 +29,7 @@ constexpr int kWave = 64;
 constexpr int kRecent = 16;
 constexpr uint32_t kHeapCap = 1024;       // requeued buckets waiting at once
 constexpr uint32_t kMaxBucket = 2048;     // largest bucket searched (its slots fit the per-wave scratch)
+constexpr uint32_t kShuffleDistinct = 1;  // buckets up to this size set their bits without the tentative step
 
 // Slot record written when a bucket is placed: owner bucket (local id), its
 // placement number, its size and its pilot.
@@ -61,9 +62,10 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
     return v;
 }
 
-// Slot within the part: reduce(h xor hp, S).
+// Slot within the part: reduce(h xor hp, S), the reduce fixed at compile time.
+template <bool Mod>
 __device__ __forceinline__ uint32_t local_slot(const DevMphf &m, uint64_t h, uint64_t hp) {
-    if (m.reduce_kind == kReduceMod) return (uint32_t)mod_reduce(h ^ hp, m.mod_slots, m.mod_magic);
+    if (Mod) return (uint32_t)mod_reduce(h ^ hp, m.mod_slots, m.mod_magic);
     return (uint32_t)(mulhi64(kMix, h ^ hp) & ((1ull << m.log2_slots) - 1));
 }
 
@@ -190,14 +192,13 @@ __device__ __forceinline__ bool distinct_lanes(uint32_t q, uint32_t s) {
 }
 
 struct LdsState {
-    uint64_t heap[kHeapCap];  // max-heap of (size << 32) | ~id
-    uint32_t heap_n;
+    uint64_t heap[kHeapCap];  // max-heap of (size << 32) | ~id; its size lives in a register
 };
 
 // Heap operations run in every lane on the same values (LDS reads
-// broadcast); lane 0 writes.
-__device__ void heap_push(LdsState &st, uint64_t v) {
-    uint32_t i = st.heap_n;
+// broadcast); lane 0 writes. hn is the heap's size (wave-uniform).
+__device__ void heap_push(LdsState &st, uint32_t &hn, uint64_t v) {
+    uint32_t i = hn;
     while (i > 0) {
         const uint32_t p = (i - 1) >> 1;
         const uint64_t pv = st.heap[p];
@@ -206,16 +207,14 @@ __device__ void heap_push(LdsState &st, uint64_t v) {
         __builtin_amdgcn_wave_barrier();
         i = p;
     }
-    if (__lane_id() == 0) {
-        st.heap[i] = v;
-        st.heap_n = st.heap_n + 1;
-    }
+    if (__lane_id() == 0) st.heap[i] = v;
+    ++hn;
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ uint64_t heap_pop(LdsState &st) {
+__device__ uint64_t heap_pop(LdsState &st, uint32_t &hn) {
     const uint64_t top = st.heap[0];
-    const uint32_t n = st.heap_n - 1;
+    const uint32_t n = hn - 1;
     const uint64_t v = st.heap[n];
     uint32_t i = 0;
     for (;;) {
@@ -229,10 +228,8 @@ __device__ uint64_t heap_pop(LdsState &st) {
         __builtin_amdgcn_wave_barrier();
         i = best;
     }
-    if (__lane_id() == 0) {
-        if (n) st.heap[i] = v;
-        st.heap_n = n;
-    }
+    if (__lane_id() == 0 && n) st.heap[i] = v;
+    hn = n;
     __builtin_amdgcn_wave_barrier();
     return top;
 }
@@ -277,6 +274,8 @@ struct Window {
 };
 
 // One wavefront per workgroup; a persistent grid takes parts from a counter.
+// Mod: the single-part x mod S reduce instead of the power-of-two one.
+template <bool Mod>
 __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
     extern __shared__ uint32_t bits[];  // S bits of the current part
     __shared__ LdsState st;
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
         if (p >= m.parts) break;
 
         for (uint32_t w = lane; w < words; w += kWave) bits[w] = 0u;
-        if (lane == 0) st.heap_n = 0;
+        uint32_t hn = 0;  // requeued buckets in the heap
         __builtin_amdgcn_wave_barrier();
 
         const uint64_t gb0 = (uint64_t)p * B;
@@ -320,10 +319,10 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                 decode_key(ow.get(k), a.max_size, a.size_bits, a.id_bits, s, id);
                 from_order = s > 0;
             }
-            if (st.heap_n > 0) {
+            if (hn > 0) {
                 const uint64_t head = from_order ? (((uint64_t)s << 32) | (0xffffffffu - id)) : 0;
                 if (st.heap[0] > head) {
-                    const uint64_t v = heap_pop(st);
+                    const uint64_t v = heap_pop(st, hn);
                     s = (uint32_t)(v >> 32);
                     id = 0xffffffffu - (uint32_t)v;
                     from_order = false;
@@ -359,10 +358,10 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                     bool free = true;
                     // four independent LDS reads per step, then one test
                     for (uint32_t j = 0; j < s; j += 4) {
-                        bool t = is_taken(bits, local_slot(m, bcast64(h0, (int)j), hp));
-                        if (j + 1 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 1), hp));
-                        if (j + 2 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 2), hp));
-                        if (j + 3 < s) t |= is_taken(bits, local_slot(m, bcast64(h0, (int)j + 3), hp));
+                        bool t = is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j), hp));
+                        if (j + 1 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 1), hp));
+                        if (j + 2 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 2), hp));
+                        if (j + 3 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 3), hp));
                         free = free && !t;
                         if (__ballot(free) == 0) break;
                     }
@@ -371,11 +370,20 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         const int lbit = __builtin_ctzll(cand);
                         cand &= cand - 1;
                         const uint32_t pc = (uint32_t)(round * kWave + lbit);
-                        // tentative: set the bits; a key that finds its bit already
-                        // set collides with a sibling (all slots were free)
+                        if (s <= kShuffleDistinct) {
+                            // the slots are free: distinct among the bucket's own
+                            // keys (lane shuffles) is all that is left to check
+                            myq = (uint32_t)lane < s ? local_slot<Mod>(m, h0, pilot_hash(m, pc)) : 0u;
+                            if (!distinct_lanes(myq, s)) continue;
+                            if ((uint32_t)lane < s) atomicOr(&bits[myq >> 5], 1u << (myq & 31));
+                            chosen = (int)pc;
+                            break;
+                        }
+                        // larger buckets: set the bits tentatively; a key that finds
+                        // its bit already set collides with a sibling (all were free)
                         bool mine = false, dup = false;
                         if ((uint32_t)lane < s) {
-                            myq = local_slot(m, h0, pilot_hash(m, pc));
+                            myq = local_slot<Mod>(m, h0, pilot_hash(m, pc));
                             const uint32_t old = atomicOr(&bits[myq >> 5], 1u << (myq & 31));
                             if (old & (1u << (myq & 31))) dup = true; else mine = true;
                         }
@@ -396,19 +404,19 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                 for (uint32_t pc = 0; pc < 256 && chosen < 0; ++pc) {
                     const uint64_t hpc = pilot_hash(m, pc);
                     bool any_taken = false;
-                    for (uint32_t t = lane; t < s; t += kWave) any_taken |= is_taken(bits, local_slot(m, src[t], hpc));
+                    for (uint32_t t = lane; t < s; t += kWave) any_taken |= is_taken(bits, local_slot<Mod>(m, src[t], hpc));
                     if (__ballot(any_taken)) continue;
                     bool dup = false;
                     uint32_t mine = 0;
                     for (uint32_t t = lane, r = 0; t < s; t += kWave, ++r) {
-                        const uint32_t qq = local_slot(m, src[t], hpc);
+                        const uint32_t qq = local_slot<Mod>(m, src[t], hpc);
                         const uint32_t old = atomicOr(&bits[qq >> 5], 1u << (qq & 31));
                         if (old & (1u << (qq & 31))) dup = true; else mine |= 1u << r;
                     }
                     if (__ballot(dup) == 0) { chosen = (int)pc; break; }
                     for (uint32_t t = lane, r = 0; t < s; t += kWave, ++r)
                         if (mine & (1u << r)) {
-                            const uint32_t qq = local_slot(m, src[t], hpc);
+                            const uint32_t qq = local_slot<Mod>(m, src[t], hpc);
                             atomicAnd(&bits[qq >> 5], ~(1u << (qq & 31)));
                         }
                     __builtin_amdgcn_wave_barrier();
@@ -428,7 +436,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         uint64_t cost = 0;
                         bool ok = true;
                         for (uint32_t j = 0; j < s; ++j) {
-                            const uint32_t qq = local_slot(m, bcast64(h0, (int)j), hp);
+                            const uint32_t qq = local_slot<Mod>(m, bcast64(h0, (int)j), hp);
                             if (ok && is_taken(bits, qq)) {
                                 const SlotRec rec = recs[qq];
                                 if ((uint64_t)rec.last + kRecent > placed) ok = false;
@@ -444,7 +452,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         mn = wave_min64(mn);
                         if (mn == ~0ull) break;
                         const uint32_t pc = (uint32_t)(mn & 255);
-                        const uint32_t qq = (uint32_t)lane < s ? local_slot(m, h0, pilot_hash(m, pc)) : 0u;
+                        const uint32_t qq = (uint32_t)lane < s ? local_slot<Mod>(m, h0, pilot_hash(m, pc)) : 0u;
                         if (distinct_lanes(qq, s)) { chosen = (int)pc; break; }
                         if ((uint32_t)lane == (pc & 63)) keyr[pc >> 6] = ~0ull;
                     }
@@ -455,7 +463,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         uint64_t cost = 0;
                         bool ok = true;
                         for (uint32_t t = lane; t < s; t += kWave) {
-                            const uint32_t qq = local_slot(m, src[t], hpc);
+                            const uint32_t qq = local_slot<Mod>(m, src[t], hpc);
                             if (is_taken(bits, qq)) {
                                 const SlotRec rec = recs[qq];
                                 if ((uint64_t)rec.last + kRecent > placed) ok = false;
@@ -466,7 +474,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         cost = wave_sum64(cost);
                         if (cost >= best) continue;
                         // distinct: write the slots to scratch, compare all pairs
-                        for (uint32_t t = lane; t < s; t += kWave) big[t] = local_slot(m, src[t], hpc);
+                        for (uint32_t t = lane; t < s; t += kWave) big[t] = local_slot<Mod>(m, src[t], hpc);
                         __threadfence_block();
                         bool dup = false;
                         for (uint32_t t = lane; t < s && !dup; t += kWave) {
@@ -485,7 +493,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                 const uint64_t hpc = pilot_hash(m, (uint32_t)chosen);
                 for (uint32_t j = 0; j < s; ++j) {
                     const uint64_t hj = small ? bcast64(h0, (int)j) : src[j];
-                    const uint32_t qq = local_slot(m, hj, hpc);
+                    const uint32_t qq = local_slot<Mod>(m, hj, hpc);
                     if (!is_taken(bits, qq)) continue;
                     const SlotRec rec = recs[qq];
                     if (rec.owner >= B || rec.size == 0 || rec.size > kMaxBucket || rec.pilot > 255) {
@@ -495,18 +503,18 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                     const uint64_t *oh = a.H + a.bst[gb0 + rec.owner];
                     const uint64_t hpo = pilot_hash(m, rec.pilot);
                     for (uint32_t t = lane; t < rec.size; t += kWave) {
-                        const uint32_t qo = local_slot(m, oh[t], hpo);
+                        const uint32_t qo = local_slot<Mod>(m, oh[t], hpo);
                         atomicAnd(&bits[qo >> 5], ~(1u << (qo & 31)));
                     }
                     __builtin_amdgcn_wave_barrier();
-                    if (st.heap_n >= kHeapCap) { status = kPlaceHeapFull; break; }
-                    heap_push(st, ((uint64_t)rec.size << 32) | (0xffffffffu - rec.owner));
+                    if (hn >= kHeapCap) { status = kPlaceHeapFull; break; }
+                    heap_push(st, hn, ((uint64_t)rec.size << 32) | (0xffffffffu - rec.owner));
                     ++ev;
                 }
                 if (status != kPlaceOk) break;
                 // the bucket's bits (phase 1 set them already)
                 for (uint32_t t = lane; t < s; t += kWave) {
-                    const uint32_t qq = local_slot(m, small ? h0 : src[t], hpc);
+                    const uint32_t qq = local_slot<Mod>(m, small ? h0 : src[t], hpc);
                     atomicOr(&bits[qq >> 5], 1u << (qq & 31));
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -516,7 +524,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             ++placed;
             const uint64_t hpc = pilot_hash(m, (uint32_t)chosen);
             const SlotRec rec{id, (uint32_t)placed, s, (uint32_t)chosen};
-            for (uint32_t t = lane; t < s; t += kWave) recs[local_slot(m, small ? h0 : src[t], hpc)] = rec;
+            for (uint32_t t = lane; t < s; t += kWave) recs[local_slot<Mod>(m, small ? h0 : src[t], hpc)] = rec;
             if (lane == 0) a.pilots[gb0 + id] = (uint8_t)chosen;
             if (ev > a.max_evictions) { status = kPlaceFailed; break; }
         }
@@ -663,10 +671,16 @@ class GpuSearch {
         if (lds_ + sizeof(LdsState) > (size_t)lds_max)
             return set_error(PTRHASH_E_RANGE, "device placement: %llu slots per part exceed the LDS of one CU",
                              (unsigned long long)S_);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&place_k),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_);
+        const void *kern = mod_ ? reinterpret_cast<const void *>(&place_k<true>)
+                                : reinterpret_cast<const void *>(&place_k<false>);
+        (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_);
         int per_cu = 0;
-        HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k, kWave, lds_), "occupancy query");
+        if (mod_)
+            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<true>, kWave, lds_),
+                        "occupancy query");
+        else
+            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<false>, kWave, lds_),
+                        "occupancy query");
         if (per_cu < 1) return set_error(PTRHASH_E_RANGE, "device placement does not fit one CU");
         grid_ = std::min<uint64_t>(P_, (uint64_t)cus * (uint64_t)per_cu);
         taken_words_ = (P_ * S_ + 63) / 64 * 2;  // u32 words, whole u64 words
@@ -799,7 +813,10 @@ class GpuSearch {
         a.next_part = next_;
         a.status = status_;
         a.evictions = ev_;
-        hipLaunchKernelGGL(place_k, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
+        if (mod_)
+            hipLaunchKernelGGL(place_k<true>, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
+        else
+            hipLaunchKernelGGL(place_k<false>, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
         HIP_OR_FAIL(hipGetLastError(), "search launch");
         status_h_.resize(P_);
         ev_h_.resize(P_);
