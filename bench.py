@@ -9,8 +9,10 @@ shuffled stream of all 10^9 members resident in HBM, u64 indices out.
 Prints ONE JSON line with queries/s, ns/key, the fraction of a measured
 random-gather roofline (the same memory pattern with no hashing), the HBM
 roofline of the query kernel, and the CPU oracle timed on a bounded sample.
-Other workloads (--workload): the 10^8 and 10^6 u64 sets, 3*10^8 byte
-strings, and the 64-MPHF serving workload.
+Other workloads (--workload): the Fast, Compact and non-minimal variants at
+10^9, the 10^8 and 10^6 u64 sets, 3*10^8 byte strings, a cache-resident
+single-part MPHF queried 10^9 times (mod or power-of-two slot reduce), and
+the 64-MPHF serving workload.
 """
 from __future__ import annotations
 
@@ -26,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x 2.4e9 cycles/s, one wave64
+# instruction per SIMD every 4 cycles (16 lanes per cycle).
+VALU_PEAK_GINSTS = 256 * 4 * 2.4 / 4
 METRIC = "queries/s (ns/key) at n=1e9 u64 keys; % of random-gather HBM roofline"
 
 WORKLOADS = {
@@ -46,6 +51,14 @@ WORKLOADS = {
     "bytes_3e8": (3 * 10**8, "bytes", 32, "n=3e8 distinct random byte strings, length uniform 10-50 over printable "
                                           "ASCII, packed with u64 offsets; shuffled stream of all members, u32 "
                                           "indices, Default params"),
+    "u64_1e5_cached_mod": (10**5, "cached", 32, "n=1e5 distinct uniform u64 keys in one part with the x mod S "
+                                                 "reduce (S=101011), 1e9 queries: the shuffled member stream "
+                                                 "repeated 1e4 times, u32 indices, Default params; the MPHF stays "
+                                                 "cache-resident"),
+    "u64_1e5_cached_pow2": (10**5, "cached", 32, "n=1e5 distinct uniform u64 keys in one part of S=2^17 slots "
+                                                  "(power-of-two reduce), 1e9 queries: the shuffled member stream "
+                                                  "repeated 1e4 times, u32 indices, Default params; the MPHF stays "
+                                                  "cache-resident"),
     "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params; "
                                  "Poisson arrivals of batches log-uniform in [1, 65536] keys, each against one "
                                  "MPHF; continuous batching"),
@@ -151,6 +164,28 @@ def profiled_traffic(workload, ms, n):
                "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": path}
 
 
+def profiled_valu(workload, ms):
+    """Vector-ALU roofline of the query kernel from the committed rocprofv3
+    counter summary of this workload (instructions per launch, counted per
+    wavefront), if the kernel sources still match the ones profiled."""
+    from paper_2502_15539_amd import profsum
+
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
+    roof = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_GINSTS, "unit": "G wave64 VALU instructions/s",
+            "frac": None, "traffic": None}
+    if not os.path.exists(path):
+        return roof
+    t = json.load(open(path))
+    if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
+        roof["stale_profile"] = path
+        return roof
+    achieved = t["valu_insts_per_launch"] / (ms / 1e3) / 1e9
+    roof.update(achieved=achieved, frac=achieved / VALU_PEAK_GINSTS, valu_insts_per_launch=t["valu_insts_per_launch"],
+                valu_busy_pct_profiled=t["valu_busy_pct"], valu_utilization_pct_profiled=t["valu_utilization_pct"],
+                source=path)
+    return roof
+
+
 def record(args, n, ms, wall, desc, extra_config, dtype, per_key, **fields):
     achieved = per_key * n / (ms / 1e3) / 1e9
     traffic, tinfo = profiled_traffic(args.workload, ms, n)
@@ -191,18 +226,29 @@ def remap_fraction(torch, P, params, pilots, queries=None, data=None, offsets=No
     return frac
 
 
-def oracle_baseline(args, p, built, q, out, bits, n):
+def oracle_mphf(P, p, built):
+    """The oracle's view of a built MPHF (same parameters, pilots and remap)."""
+    from oracle import oracle as O
+
+    if p.reduce_kind == P.REDUCE_MOD:
+        op = O.params_single_mod(p.n, S=p.slots, B=p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    else:
+        op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    return O.Mphf(op, built.pilots, None, built.remap, None)
+
+
+def oracle_baseline(args, p, built, q, out, bits, n, P=None):
     """The oracle's plain query loop on the first args.cpu_sample queries of the
     same stream and MPHF: once on one thread, once split over the host's cores
     (one slice per thread; the C loop runs outside the GIL)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
+    from paper_2502_15539_amd import ptrhash as PH
 
-    ns = min(args.cpu_sample, n)
+    ns = min(args.cpu_sample, len(q))
     qs = q[:ns].cpu().numpy().view(np.uint64)
-    op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
-    m = O.Mphf(op, built.pilots, None, built.remap, None)
+    m = oracle_mphf(P or PH, p, built)
     one = qs[: max(1, ns // 4)]
     c0 = time.perf_counter()
     O.query_u64(m, one, O.REMAP_CLEF)
@@ -270,8 +316,8 @@ def run_u64(args, torch, K, P):
     dev = "cuda"
     threads = args.threads or min(16, os.cpu_count() or 1)
     t0 = time.time()
-    # the key set is generated in HBM; construction hashes and sorts it on the
-    # device and runs the pilot search on host threads
+    # the key set is generated in HBM; construction hashes and sorts it and
+    # runs the pilot search on the device
     keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=dev), K.KEY_SEED)
     torch.cuda.synchronize()
     t1 = time.time()
@@ -343,6 +389,65 @@ def run_u64(args, torch, K, P):
     if args.workload != "u64_1e9":
         rec["metric"] = f"queries/s (ns/key) at n={n:.0e} u64 keys"
     return rec, bij and (cpu is None or cpu["matches_gpu"])
+
+
+def run_cached(args, torch, K, P):
+    """A small single-part MPHF queried 10^9 times: its pilots and remap stay in
+    the caches, so the time is the kernel's arithmetic plus the key and index
+    streams. The _mod and _pow2 workloads differ only in the slot reduce."""
+    n, _, bits, desc = WORKLOADS[args.workload]
+    dev = "cuda"
+    reps = 10**4
+    n_q = n * reps
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=dev), K.KEY_SEED)
+    mod = args.workload.endswith("_mod")
+    params = P.params_default(n, P.PRESET_DEFAULT | (P.PRESET_SINGLE_MOD if mod else 0), index_bits=bits)
+    t1 = time.time()
+    built = P.build_u64_device(keys, params=params)
+    t2 = time.time()
+    p = built.params
+    assert p.num_parts == 1 and (p.reduce_kind == P.REDUCE_MOD) == mod
+    log(f"[bench] build {t2 - t1:.2f}s ({built.placement} search) S={p.slots_per_part} B={p.buckets_per_part} "
+        f"reduce={'mod' if mod else 'pow2'} bits/key={built.bits_per_key:.3f}")
+    mphf = P.Mphf.from_built(built)
+    period = torch.empty(n, dtype=torch.int64, device=dev)
+    P.gen_query_stream(period, n, K.KEY_SEED, K.ORDER_SEED)
+    q = period.repeat(reps)
+    out = torch.empty(n_q, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_into(q, out), args, n_q)
+    head = out[:n]
+    bij = bijective(torch, head, n)
+    periodic = bool((out.view(reps, n) == head).all())
+    gout = torch.empty(n_q, dtype=torch.int64, device=dev)
+    copy_ms = min(time_launches(torch, lambda: P.bench_copy(q, gout, k, 256), 3, 1) for k in (1, 4, 8))
+    del gout
+    log(f"[bench] query {ms:.3f} ms  copy (16 B/key) {copy_ms:.3f} ms  bijective={bij} periodic={periodic}")
+
+    from oracle import oracle as O
+
+    want = O.query_u64(oracle_mphf(P, p, built), period.cpu().numpy().view(np.uint64), O.REMAP_CLEF)
+    first = bool(np.array_equal(head.cpu().numpy().view(np.uint32).astype(np.uint64), want))
+    cpu = oracle_baseline(args, p, built, q, out, bits, n_q, P) if args.cpu_sample else None
+    per_key = 8 + bits // 8  # key in, index out; the tables are served by the caches
+    rec = record(args, n_q, ms, wall, desc,
+                 {"kernel": kernel_name(P, best), "index_bits": bits, "keys": n, "num_slots": p.slots_per_part,
+                  "reduce": "mod" if mod else "pow2", "buckets_per_part": p.buckets_per_part,
+                  "bits_per_key": round(built.bits_per_key, 4)},
+                 "u64", per_key,
+                 stream_copy_ms=copy_ms,
+                 plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
+                 cpu_baseline=cpu,
+                 parity={"bijective_members": bij, "every_period_equal": periodic,
+                         "first_period_equals_oracle": first},
+                 build_s=t2 - t1, build_search=built.placement)
+    # the tables are cache-resident and the streams take 12 B/key: the kernel's
+    # vector arithmetic bounds it, so the roofline is the VALU issue rate
+    rec["stream_roofline"] = rec["roofline"]
+    rec["roofline"] = profiled_valu(args.workload, ms)
+    rec["metric"] = f"queries/s (ns/key): 1e9 queries against a cache-resident n=1e5 MPHF ({rec['config']['reduce']} reduce)"
+    return rec, bij and periodic and first and (cpu is None or cpu["matches_gpu"])
 
 
 def run_bytes(args, torch, K, P):
@@ -419,7 +524,7 @@ def main():
         sys.exit(1)
     P.lib()  # fail loudly if the HIP library is missing
     kind = WORKLOADS[args.workload][1]
-    run = {"u64": run_u64, "bytes": run_bytes, "serve": run_serve}[kind]
+    run = {"u64": run_u64, "cached": run_cached, "bytes": run_bytes, "serve": run_serve}[kind]
     rec, ok = run(args, torch, K, P)
     print(json.dumps(rec), flush=True)
     if not ok:

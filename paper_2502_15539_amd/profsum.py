@@ -11,6 +11,10 @@
         kernel (reading and writing N bytes) onto N, or by the factors of an
         earlier traffic JSON of the same device; the JSON records a hash of
         the kernel sources so that a later change voids it.
+    python -m paper_2502_15539_amd.profsum valu --db DB --kernel SUBSTR --out JSON
+        vector-ALU instructions per launch of a kernel (SQ_INSTS_VALU, counted
+        per wavefront) with the VALUBusy and VALUUtilization metrics, and the
+        same source hash.
 """
 from __future__ import annotations
 
@@ -89,6 +93,16 @@ def traffic(args) -> dict:
     return res
 
 
+def valu(args) -> dict:
+    res = {"kernel": args.kernel, "valu_insts_per_launch": _mean(args.db, args.kernel, "SQ_INSTS_VALU"),
+           "valu_busy_pct": _mean(args.db, args.kernel, "VALUBusy"),
+           "valu_utilization_pct": _mean(args.db, args.kernel, "VALUUtilization"),
+           "kernel_source_sha256": kernel_source_hash()}
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -104,11 +118,17 @@ def main():
     r.add_argument("--copy-bytes", type=float)
     r.add_argument("--scale-from", help="take the scale factors of this traffic JSON")
     r.add_argument("--out", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--db", required=True)
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
         print(trace(a.db))
     elif a.cmd == "counters":
         print(counters(a.dbs))
+    elif a.cmd == "valu":
+        print(json.dumps(valu(a), indent=1))
     else:
         print(json.dumps(traffic(a), indent=1))
 
