@@ -157,17 +157,19 @@ def profiled_traffic(workload, ms, n):
         return None, None
     t = json.load(open(path))
     if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
-        return None, {"stale_profile": path}
+        return None, {"stale_profile": os.path.relpath(path, ROOT)}
     b = t["traffic_bytes_per_launch"]
     return b, {"traffic_GBps": b / (ms / 1e3) / 1e9, "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                "traffic_bytes_per_key": b / n,
-               "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": path}
+               "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": os.path.relpath(path, ROOT)}
 
 
-def profiled_valu(workload, ms):
+def profiled_valu(workload, ms, kernel):
     """Vector-ALU roofline of the query kernel from the committed rocprofv3
     counter summary of this workload (instructions per launch, counted per
-    wavefront), if the kernel sources still match the ones profiled."""
+    wavefront), if the kernel sources still match the ones profiled and the
+    profiled kernel takes as many keys per lane as the timed one (the count
+    depends on that, not on the workgroup size)."""
     from paper_2502_15539_amd import profsum
 
     path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
@@ -177,12 +179,15 @@ def profiled_valu(workload, ms):
         return roof
     t = json.load(open(path))
     if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
-        roof["stale_profile"] = path
+        roof["stale_profile"] = os.path.relpath(path, ROOT)
+        return roof
+    if t.get("kernel") != kernel:
+        roof["profiled_kernel"] = t.get("kernel")
         return roof
     achieved = t["valu_insts_per_launch"] / (ms / 1e3) / 1e9
     roof.update(achieved=achieved, frac=achieved / VALU_PEAK_GINSTS, valu_insts_per_launch=t["valu_insts_per_launch"],
                 valu_busy_pct_profiled=t["valu_busy_pct"], valu_utilization_pct_profiled=t["valu_utilization_pct"],
-                source=path)
+                source=os.path.relpath(path, ROOT))
     return roof
 
 
@@ -445,7 +450,8 @@ def run_cached(args, torch, K, P):
     # the tables are cache-resident and the streams take 12 B/key: the kernel's
     # vector arithmetic bounds it, so the roofline is the VALU issue rate
     rec["stream_roofline"] = rec["roofline"]
-    rec["roofline"] = profiled_valu(args.workload, ms)
+    timed = f"query_pipelined<{best[1]}, unsigned int>" if best[0] == P.KERNEL_PIPELINED else "query_plain"
+    rec["roofline"] = profiled_valu(args.workload, ms, timed)
     rec["metric"] = f"queries/s (ns/key): 1e9 queries against a cache-resident n=1e5 MPHF ({rec['config']['reduce']} reduce)"
     return rec, bij and periodic and first and (cpu is None or cpu["matches_gpu"])
 

@@ -11,9 +11,10 @@
 //  - query_plain: one key per lane, the straightforward form.
 //  - query_pipelined<K>: K keys per lane in a tile of K*blockDim keys; all
 //    K key loads, then all K pilot gathers, are issued before any result is
-//    used, and the remap lines of the K keys are fetched together in one
-//    round trip. Keys and indices are streamed with non-temporal loads and
-//    stores so that they do not evict pilots from the L2 and MALL.
+//    used (both unconditionally, so that none waits inside a branch). The
+//    rare remap reads stay under their slot >= n branch. Keys and indices
+//    are streamed with non-temporal loads and stores so that they do not
+//    evict pilots from the L2 and MALL.
 //  - query_bytes<K>: the same for packed byte-string keys.
 //  - query_multi: a persistent launch over many batches, each against its
 //    own resident MPHF, described by a table in device memory.
@@ -41,8 +42,8 @@ __global__ void __launch_bounds__(1024) query_plain(const uint64_t *__restrict__
     out[i] = (OutT)v;
 }
 
-// Slots of K keys (already hashed) -> indices, with the remap loads of all
-// K keys issued before any is decoded.
+// Slots of K keys (already hashed) -> indices: keys with slot >= n read and
+// decode their remap entry (divergent; about 1 % of the keys).
 template <int K>
 __device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], const bool (&ok)[K]) {
     if (m.remap_kind == kRemapNone) return;
@@ -79,27 +80,38 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
                                              uint64_t nq, OutT *__restrict__ out, uint64_t base, uint32_t stride) {
     uint64_t h[K], hs[K];  // hash for part/bucket, hash for the slot
     bool ok[K];
+    if (Bytes) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint64_t i = base + (uint64_t)j * stride;
-        ok[j] = i < nq;
-        if (Bytes) {
+        for (int j = 0; j < K; ++j) {
+            const uint64_t i = base + (uint64_t)j * stride;
+            ok[j] = i < nq;
             if (ok[j]) {
                 const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
                 h[j] = hash_bytes(m.seed, data, o0, o1 - o0, m.hash128 != 0, hs[j]);
             } else {
                 h[j] = hs[j] = 0;
             }
-        } else {
-            h[j] = hs[j] = ok[j] ? hash_u64(nt_load(keys + i)) : 0;
         }
+    } else {
+        // Every lane loads all K keys unconditionally (a lane past the end
+        // reads key 0; nq >= 1), so that the K loads are issued back to back
+        // and waited for once: a load under a branch is waited for inside
+        // the branch.
+        uint64_t key[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t i = base + (uint64_t)j * stride;
+            ok[j] = i < nq;
+            key[j] = nt_load(keys + (ok[j] ? i : 0));
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) h[j] = hs[j] = hash_u64(key[j]);
     }
+    // Any hash maps to a bucket inside the table, so the K pilot gathers are
+    // unconditional too.
     uint32_t part[K], pil[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint64_t b = bucket_of(m, h[j], part[j]);
-        pil[j] = ok[j] ? m.pilots[b] : 0;
-    }
+    for (int j = 0; j < K; ++j) pil[j] = m.pilots[bucket_of(m, h[j], part[j])];
     uint64_t v[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) v[j] = slot_of(m, hs[j], part[j], pil[j]);

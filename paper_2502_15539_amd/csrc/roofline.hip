@@ -14,15 +14,17 @@ __global__ void __launch_bounds__(1024) bench_gather_k(const uint64_t *__restric
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
     uint64_t k[K];
     bool ok[K];
+    // unconditional loads, as in the query kernel: a lane past the end reads
+    // key 0 (nq >= 1), and hi(k * T) < T for every k
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * blockDim.x;
         ok[j] = i < nq;
-        k[j] = ok[j] ? __builtin_nontemporal_load(keys + i) : 0;
+        k[j] = __builtin_nontemporal_load(keys + (ok[j] ? i : 0));
     }
     uint32_t b[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) b[j] = ok[j] ? table[__umul64hi(k[j], T)] : 0;
+    for (int j = 0; j < K; ++j) b[j] = table[__umul64hi(k[j], T)];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * blockDim.x;
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(1024) bench_copy_k(const uint64_t *__restrict_
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * blockDim.x;
-        k[j] = i < nq ? __builtin_nontemporal_load(keys + i) : 0;
+        k[j] = __builtin_nontemporal_load(keys + (i < nq ? i : 0));
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -49,7 +51,8 @@ __global__ void __launch_bounds__(1024) bench_copy_k(const uint64_t *__restrict_
 
 // Random byte gathers with no streams: index i is hi(mix(i) * T) (SplitMix64
 // output mixer), four gathers in flight per lane per step, one u32 sum per
-// lane written at the end so the loads stay live.
+// lane written at the end so the loads stay live. hi(x * T) < T for every x,
+// so the loads past the end are in bounds and only their values are dropped.
 __device__ inline uint64_t sm_mix(uint64_t z) {
     z ^= z >> 30;
     z *= 0xbf58476d1ce4e5b9ull;
@@ -69,7 +72,8 @@ __global__ void __launch_bounds__(256) bench_gather_pure_k(uint64_t n, const uin
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint64_t k = i + j * stride;
-            b[j] = k < n ? table[__umul64hi(sm_mix(k), T)] : 0;
+            b[j] = table[__umul64hi(sm_mix(k), T)];
+            b[j] = k < n ? b[j] : 0;
         }
         acc += b[0] + b[1] + b[2] + b[3];
     }
@@ -91,7 +95,8 @@ __global__ void __launch_bounds__(256) bench_gather_pair_k(uint64_t n, const uin
         for (int j = 0; j < 4; ++j) {
             const uint64_t k = i + j * stride;
             const uint64_t o = __umul64hi(sm_mix(k), T);
-            b[j] = k < n ? table[o] + table[o ^ D] : 0;
+            b[j] = table[o] + table[o ^ D];
+            b[j] = k < n ? b[j] : 0;
         }
         acc += b[0] + b[1] + b[2] + b[3];
     }

@@ -29,11 +29,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/kernels.hip", "csrc/mphf_device.h"]
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and blank lines, so that a comment edit
+    does not void a profile."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line.strip())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
