@@ -59,7 +59,8 @@ WORKLOADS = {
                                                   "(power-of-two reduce), 1e9 queries: the shuffled member stream "
                                                   "repeated 1e4 times, u32 indices, Default params; the MPHF stays "
                                                   "cache-resident"),
-    "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params; "
+    "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params (the "
+                                 "23 that get one part use the x mod S reduce); "
                                  "Poisson arrivals of batches log-uniform in [1, 65536] keys, each against one "
                                  "MPHF; continuous batching"),
 }

@@ -32,16 +32,23 @@ from . import keygen as K
 from . import ptrhash as P
 
 
-def build_fleet(count=64, lo=10**4, hi=10**7, seed=5, threads=0, log=print):
+def build_fleet(count=64, lo=10**4, hi=10**7, seed=5, threads=0, single_mod=True, log=print):
+    """count MPHFs with log-uniform sizes in [lo, hi], Default parameters.
+    single_mod: an MPHF that the parameter rule gives a single part uses the
+    x mod S reduce with S ~ n/alpha (load ~0.99) instead of the next power of
+    two (load down to ~0.5), which keeps its remap fraction near 1 %."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(np.log(lo) + rng.uniform(0, 1, size=count) * np.log(hi / lo)).astype(np.int64)
+    preset = P.PRESET_DEFAULT | (P.PRESET_SINGLE_MOD if single_mod else 0)
     fleet = []
     t0 = time.time()
     for j, n in enumerate(sizes):
         keys = K.u64_keys(int(n), seed=1000 + j)
-        b = P.build_u64(keys, index_bits=32, threads=threads)
+        b = P.build_u64(keys, index_bits=32, threads=threads, preset=preset)
         fleet.append((keys, P.Mphf.from_built(b)))
-    log(f"[serve] built {count} MPHFs, {int(sizes.sum())} keys in {time.time() - t0:.1f}s")
+    single = sum(1 for _, m in fleet if m.params.reduce_kind == P.REDUCE_MOD)
+    log(f"[serve] built {count} MPHFs ({single} single-part with the mod reduce), {int(sizes.sum())} keys in "
+        f"{time.time() - t0:.1f}s")
     return fleet
 
 
