@@ -11,8 +11,9 @@ random-gather roofline (the same memory pattern with no hashing), the HBM
 roofline of the query kernel, and the CPU oracle timed on a bounded sample.
 Other workloads (--workload): the Fast, Compact and non-minimal variants at
 10^9, the 10^8 and 10^6 u64 sets, 3*10^8 byte strings, a cache-resident
-single-part MPHF queried 10^9 times (mod or power-of-two slot reduce), and
-the 64-MPHF serving workload.
+single-part MPHF queried 10^9 times (mod or power-of-two slot reduce), one
+multi-MPHF launch over 4096 device-resident requests, and the 64-MPHF
+serving workload.
 """
 from __future__ import annotations
 
@@ -59,6 +60,10 @@ WORKLOADS = {
                                                   "(power-of-two reduce), 1e9 queries: the shuffled member stream "
                                                   "repeated 1e4 times, u32 indices, Default params; the MPHF stays "
                                                   "cache-resident"),
+    "multi_c5": (0, "multi", 32, "4096 requests against the 64-MPHF serving fleet (n log-uniform in [1e4, 1e7] u64 "
+                                 "keys, Default params, the single-part ones with the x mod S reduce; batch sizes "
+                                 "log-uniform in [1, 65536], 24.1M member keys drawn with replacement), resident in "
+                                 "HBM, all answered by one multi-MPHF launch per step"),
     "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params (the "
                                  "23 that get one part use the x mod S reduce); "
                                  "Poisson arrivals of batches log-uniform in [1, 65536] keys, each against one "
@@ -498,6 +503,98 @@ def run_bytes(args, torch, K, P):
     return rec, bij and (cpu is None or cpu["matches_gpu"])
 
 
+def run_multi(args, torch, K, P):
+    """One multi-MPHF launch over 4096 device-resident requests (each against
+    its own resident MPHF) per step, with the launch shape the autotuner
+    picks; parity: equal to one plain query per request and to the oracle on
+    every request."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    from paper_2502_15539_amd import autotune, serving
+
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    fleet = serving.build_fleet(threads=threads, log=log)
+    reqs, js = serving.make_requests(fleet, P.multi_max(), with_index=True)
+    n_keys = sum(len(q) for _, q, _ in reqs)
+    dev = [(m, torch.from_numpy(q.view(np.int64)).to("cuda"), torch.empty(len(q), dtype=torch.int32, device="cuda"))
+           for m, q, _ in reqs]
+    plan = P.MultiPlan(len(dev))
+    cands = None
+    if args.kernel not in ("auto", "plain"):
+        v = [int(x) for x in args.kernel.split(",")]
+        cands = [(v[0], v[1], v[2] if len(v) > 2 else 0)]
+    shape, sweep = autotune.tune_multi(torch, plan, dev, cands=cands, use_cache=False)
+    log("[bench] multi shape sweep (keys-per-lane/block/blocks-per-cu): " +
+        ", ".join(f"{c[0]}/{c[1]}/{c[2]}={v:.4f}ms" for c, v in sorted(sweep.items())))
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    got = [o.clone() for _, _, o in dev]
+
+    # parity: one plain launch per request, and the oracle on every request
+    for m, q, o in dev:
+        m.set_kernel(P.KERNEL_PLAIN, 1, 256)
+        m.query_into(q, o)
+    torch.cuda.synchronize()
+    plain_equal = all(torch.equal(a, o) for a, (_, _, o) in zip(got, dev))
+    oracles = [oracle_mphf(P, b.params, b) for _, _, b in fleet]
+    host = [g.cpu().numpy().view(np.uint32).astype(np.uint64) for g in got]
+    # slot >= n fraction of the requests' keys (non-minimal view of the same pilots)
+    phf = {}
+    remapped = 0
+    for (m, q, _), j in zip(dev, js):
+        if j not in phf:
+            b = fleet[j][2]
+            pp = b.params.copy()
+            pp.remap_kind = P.REMAP_NONE
+            pp.index_bits = 64
+            phf[j] = P.Mphf().load(pp, b.pilots, None)
+        remapped += int((phf[j].query(q) >= fleet[j][2].params.n).sum().item())
+    for h in phf.values():
+        h.close()
+    rfrac = remapped / n_keys
+
+    def check(i):
+        q = reqs[i][1]
+        return np.array_equal(O.query_u64(oracles[js[i]], q, O.REMAP_CLEF), host[i])
+
+    cpu = None
+    with ThreadPoolExecutor(threads) as ex:
+        c0 = time.perf_counter()
+        oracle_equal = all(ex.map(check, range(len(reqs))))
+        cdt = time.perf_counter() - c0
+    if args.cpu_sample:
+        cpu = {"value": n_keys / cdt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "ns_per_key": cdt / n_keys * 1e9,
+               "sample": f"all {len(reqs)} requests ({n_keys} keys): the C oracle's plain query loop per request, "
+                         f"requests spread over {threads} threads",
+               "matches_gpu": oracle_equal}
+    plan.close()
+    log(f"[bench] multi launch {ms:.4f} ms ({n_keys / ms / 1e6:.1f} G keys/s, shape {shape}) remap_frac={rfrac:.4f} "
+        f"plain_equal={plain_equal} oracle_equal={oracle_equal} (oracle {cdt / n_keys * 1e9:.2f} ns/key)")
+    per_key = 8 + 4 + 1 + rfrac * 64
+    rec = record(args, n_keys, ms, wall, WORKLOADS["multi_c5"][3],
+                 {"requests": len(reqs), "mphfs": len(fleet), "resident_keys": int(sum(len(f[0]) for f in fleet)),
+                  "multi_shape": {"keys_per_lane": shape[0], "block": shape[1], "blocks_per_cu": shape[2]},
+                  "index_bits": 32},
+                 "u64", per_key, cpu_baseline=cpu,
+                 parity={"multi_equals_plain": plain_equal, "multi_equals_oracle": oracle_equal,
+                         "remap_fraction": rfrac},
+                 shape_sweep_ms={f"{c[0]}/{c[1]}/{c[2]}": v for c, v in sorted(sweep.items())})
+    rec["metric"] = "queries/s of one multi-MPHF launch over 4096 device-resident requests (64 MPHFs)"
+    return rec, plain_equal and oracle_equal
+
+
 def run_serve(args, torch, K, P):
     from paper_2502_15539_amd import serving
 
@@ -531,7 +628,7 @@ def main():
         sys.exit(1)
     P.lib()  # fail loudly if the HIP library is missing
     kind = WORKLOADS[args.workload][1]
-    run = {"u64": run_u64, "cached": run_cached, "bytes": run_bytes, "serve": run_serve}[kind]
+    run = {"u64": run_u64, "cached": run_cached, "bytes": run_bytes, "multi": run_multi, "serve": run_serve}[kind]
     rec, ok = run(args, torch, K, P)
     print(json.dumps(rec), flush=True)
     if not ok:

@@ -33,7 +33,8 @@ from . import ptrhash as P
 
 
 def build_fleet(count=64, lo=10**4, hi=10**7, seed=5, threads=0, single_mod=True, log=print):
-    """count MPHFs with log-uniform sizes in [lo, hi], Default parameters.
+    """count MPHFs with log-uniform sizes in [lo, hi], Default parameters:
+    a list of (keys, resident Mphf, Built).
     single_mod: an MPHF that the parameter rule gives a single part uses the
     x mod S reduce with S ~ n/alpha (load ~0.99) instead of the next power of
     two (load down to ~0.5), which keeps its remap fraction near 1 %."""
@@ -45,23 +46,26 @@ def build_fleet(count=64, lo=10**4, hi=10**7, seed=5, threads=0, single_mod=True
     for j, n in enumerate(sizes):
         keys = K.u64_keys(int(n), seed=1000 + j)
         b = P.build_u64(keys, index_bits=32, threads=threads, preset=preset)
-        fleet.append((keys, P.Mphf.from_built(b)))
-    single = sum(1 for _, m in fleet if m.params.reduce_kind == P.REDUCE_MOD)
+        fleet.append((keys, P.Mphf.from_built(b), b))
+    single = sum(1 for _, _, b in fleet if b.params.reduce_kind == P.REDUCE_MOD)
     log(f"[serve] built {count} MPHFs ({single} single-part with the mod reduce), {int(sizes.sum())} keys in "
         f"{time.time() - t0:.1f}s")
     return fleet
 
 
-def make_requests(fleet, count, seed=6, max_size=65536):
+def make_requests(fleet, count, seed=6, max_size=65536, with_index=False):
+    """count requests (Mphf, member keys drawn with replacement, u32 output
+    array); with_index also returns each request's fleet index."""
     rng = np.random.default_rng(seed)
-    reqs = []
+    reqs, js = [], []
     for _ in range(count):
         j = int(rng.integers(len(fleet)))
-        keys, m = fleet[j]
+        keys, m = fleet[j][:2]
         size = min(max_size, max(1, int(np.exp(rng.uniform(0, np.log(max_size))))))
         q = keys[rng.integers(0, len(keys), size=size)]
         reqs.append((m, q, np.zeros(size, dtype=np.uint32)))
-    return reqs
+        js.append(j)
+    return (reqs, js) if with_index else reqs
 
 
 def poisson_arrivals(count, rate_per_s, seed):
@@ -219,7 +223,7 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
         f"agree={agree}")
     return {"batched_on_device": batched, "saturated": sat, "open_loop": runs, "plain_per_request": base,
             "served_equals_plain": agree,
-            "mphfs": len(fleet), "resident_keys": int(sum(len(k) for k, _ in fleet)),
+            "mphfs": len(fleet), "resident_keys": int(sum(len(f[0]) for f in fleet)),
             "server_config": {"streams": streams, "slot_keys": slot, "copy_threads": copiers, "zero_copy": zc,
                               "mapped_requests": mp, "max_batches": 1024, "multi_shape": list(shape)},
             "saturated_copied_requests": tried[best_copied],
