@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -156,23 +157,36 @@ int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint
         }
     }
     uint32_t c = 0;
+    for (int i = 0; i < k; ++i) c += descs[i].n_q != 0;
+    t->count = c;  // fixes where the arrays after the header start
+    uint64_t *tb = multi_tile_begin(t);
+    MultiBatch *bt = multi_batches(t);
+    DevMphf *mp = multi_mphfs(t);
+    // each distinct handle once; requests for the same MPHF usually repeat
+    // the previous handle, so a small map of recent handles is enough
+    std::unordered_map<const ptrhash_handle *, uint32_t> index;
+    uint32_t j = 0, mphfs = 0;
     uint64_t tiles = 0;
     for (int i = 0; i < k; ++i) {
         const ptrhash_query_desc &d = descs[i];
         if (d.n_q == 0) continue;
-        MultiDesc &m = t->descs[c++];
-        m.m = device_view(d.handle);
-        m.bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
-        m.out64 = d.handle->params.index_bits == 64;
-        m.keys = m.bytes ? nullptr : d.keys;
-        m.data = m.bytes ? d.data : nullptr;
-        m.offsets = m.bytes ? d.offsets : nullptr;
-        m.out = d.out;
-        m.nq = d.n_q;
-        m.tile_begin = tiles;
+        auto it = index.find(d.handle);
+        if (it == index.end()) {
+            it = index.emplace(d.handle, mphfs).first;
+            mp[mphfs++] = device_view(d.handle);
+        }
+        const bool bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
+        MultiBatch &b = bt[j];
+        b.keys = bytes ? static_cast<const void *>(d.data) : static_cast<const void *>(d.keys);
+        b.offsets = bytes ? d.offsets : nullptr;
+        b.out = d.out;
+        b.nq = d.n_q;
+        b.mphf = it->second;
+        b.flags = (bytes ? kBatchBytes : 0u) | (d.handle->params.index_bits == 64 ? kBatchOut64 : 0u);
+        tb[j++] = tiles;
         tiles += (d.n_q + tile - 1) / tile;
     }
-    t->count = c;
+    t->mphfs = mphfs;
     t->tile = tile;
     t->tiles = tiles;
     return PTRHASH_OK;
@@ -437,7 +451,7 @@ PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **ou
     ptrhash_multi_plan *p = new (std::nothrow) ptrhash_multi_plan();
     if (!p) return fail(PTRHASH_E_NOMEM, "plan allocation failed");
     p->max = max_descs;
-    const size_t bytes = multi_table_bytes(max_descs);
+    const size_t bytes = multi_table_capacity(max_descs);
     hipError_t e = hipMalloc(&p->d_table, bytes);
     if (e != hipSuccess) {
         p->d_table = nullptr;
@@ -454,7 +468,7 @@ PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **ou
     p->tuning = multi_default_tuning();
     p->h_stage->tile = multi_tile(p->tuning);
     p->grid = multi_grid(p->tuning);
-    p->used_bytes = multi_table_bytes(1);
+    p->used_bytes = multi_table_bytes(0, 0);
     *out = p;
     return PTRHASH_OK;
 }
@@ -465,8 +479,7 @@ PTRHASH_API int ptrhash_multi_plan_set(ptrhash_multi_plan *plan, const ptrhash_q
     if (k > plan->max) return fail(PTRHASH_E_RANGE, "%d batches exceed the plan's %d", k, plan->max);
     const int rc = fill_multi_table(plan->h_stage, descs, k, multi_tile(plan->tuning));
     if (rc) return rc;
-    const uint32_t c = plan->h_stage->count;
-    plan->used_bytes = multi_table_bytes(c ? (int)c : 1);
+    plan->used_bytes = multi_table_bytes(plan->h_stage->count, plan->h_stage->mphfs);
     return PTRHASH_OK;
 }
 
@@ -503,7 +516,7 @@ PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t 
     const bool capturing = cs != hipStreamCaptureStatusNone;
     if (!capturing && plan->h_stage->tiles == 0) return PTRHASH_OK;
     // a captured copy must cover any later table, so it copies all of it
-    const size_t bytes = capturing ? multi_table_bytes(plan->max) : plan->used_bytes;
+    const size_t bytes = capturing ? multi_table_capacity(plan->max) : plan->used_bytes;
     e = hipMemcpyAsync(plan->d_table, plan->h_stage, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "batch table copy");
     e = launch_query_multi(plan->d_table, plan->tuning, plan->grid, stream);

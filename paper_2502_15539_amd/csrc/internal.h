@@ -32,26 +32,56 @@ bool valid_multi_tuning(int keys_per_lane, int block, int blocks_per_cu);
 inline uint32_t multi_tile(const MultiTuning &t) { return (uint32_t)t.keys_per_lane * (uint32_t)t.block; }
 MultiTuning multi_default_tuning();  // the process-wide default (ptrhash_set_multi_kernel)
 
-struct MultiDesc {
-    DevMphf m;
-    const uint64_t *keys;     // u64 keys (bytes == 0)
-    const uint8_t *data;      // byte keys (bytes == 1)
-    const uint64_t *offsets;
+// One batch of a multi-MPHF launch (40 bytes).
+struct MultiBatch {
+    const void *keys;         // u64 keys, or the packed bytes of byte keys
+    const uint64_t *offsets;  // byte keys: nq + 1 offsets into keys
     void *out;
     uint64_t nq;
-    uint64_t tile_begin;      // first global tile of this batch
-    uint32_t bytes, out64;
+    uint32_t mphf;            // index into the table's MPHF array
+    uint32_t flags;           // kBatchBytes | kBatchOut64
 };
+enum : uint32_t { kBatchBytes = 1, kBatchOut64 = 2 };
 
+// The batches of one multi-MPHF launch, laid out back to back after this
+// header: tile_begin[count] (first global tile of each batch, ascending),
+// batch[count], then mphf[mphfs] (each distinct MPHF once). The kernel's
+// binary search touches only the compact tile_begin array, and a table of
+// many batches over few MPHFs stays small to upload.
 struct MultiTable {
-    uint32_t count;           // batches (>= 1)
-    uint32_t tile;            // keys per tile the table was numbered with
-    uint64_t tiles;           // total tiles
-    MultiDesc descs[1];       // count entries follow
+    uint32_t count;  // batches
+    uint32_t tile;   // keys per tile the table was numbered with
+    uint64_t tiles;  // total tiles
+    uint32_t mphfs;  // distinct MPHFs
+    uint32_t pad_[3];
 };
+static_assert(sizeof(MultiTable) == 32 && sizeof(MultiBatch) == 40, "multi table layout");
 
-inline size_t multi_table_bytes(int max_descs) {
-    return sizeof(MultiTable) + sizeof(MultiDesc) * (size_t)(max_descs > 1 ? max_descs - 1 : 0);
+__host__ __device__ inline uint64_t *multi_tile_begin(MultiTable *t) { return reinterpret_cast<uint64_t *>(t + 1); }
+__host__ __device__ inline const uint64_t *multi_tile_begin(const MultiTable *t) {
+    return reinterpret_cast<const uint64_t *>(t + 1);
+}
+__host__ __device__ inline MultiBatch *multi_batches(MultiTable *t) {
+    return reinterpret_cast<MultiBatch *>(multi_tile_begin(t) + t->count);
+}
+__host__ __device__ inline const MultiBatch *multi_batches(const MultiTable *t) {
+    return reinterpret_cast<const MultiBatch *>(multi_tile_begin(t) + t->count);
+}
+__host__ __device__ inline DevMphf *multi_mphfs(MultiTable *t) {
+    return reinterpret_cast<DevMphf *>(multi_batches(t) + t->count);
+}
+__host__ __device__ inline const DevMphf *multi_mphfs(const MultiTable *t) {
+    return reinterpret_cast<const DevMphf *>(multi_batches(t) + t->count);
+}
+
+// Bytes of a table of `count` batches over `mphfs` distinct MPHFs, and the
+// most a table of up to max_batches batches can take.
+inline size_t multi_table_bytes(uint32_t count, uint32_t mphfs) {
+    return sizeof(MultiTable) + (size_t)count * (sizeof(uint64_t) + sizeof(MultiBatch)) + (size_t)mphfs * sizeof(DevMphf);
+}
+inline size_t multi_table_capacity(int max_batches) {
+    const uint32_t m = max_batches > 0 ? (uint32_t)max_batches : 0;
+    return multi_table_bytes(m, m);
 }
 
 // The table must have been filled with multi_tile(t); grid from multi_grid(t).

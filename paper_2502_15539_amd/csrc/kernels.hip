@@ -140,41 +140,46 @@ __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict_
 
 // Persistent launch over a table of query batches (each against its own
 // resident MPHF). Every batch is cut into tiles of K*blockDim keys (the
-// table records the tile size it was numbered with);
-// tiles are numbered globally (MultiDesc::tile_begin is a prefix sum) and
-// the grid strides over them, so batches of any mix of sizes share one
-// launch. The header (batch count, tile count) lives in device memory next
-// to the batches, so a captured launch can be replayed over new batches.
+// table records the tile size it was numbered with); tiles are numbered
+// globally (tile_begin is a prefix sum) and the grid strides over them, so
+// batches of any mix of sizes share one launch. The header (batch count,
+// tile count) lives in device memory next to the batches, so a captured
+// launch can be replayed over new batches.
 template <int K>
 __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict__ table) {
     const uint32_t count = table->count;
     const uint64_t tiles = table->tiles;
     const uint32_t tile = table->tile;
     if (tile != (uint32_t)K * blockDim.x) return;  // table numbered for another launch shape
-    const MultiDesc *__restrict__ d = table->descs;
+    const uint64_t *__restrict__ tb = multi_tile_begin(table);
+    const MultiBatch *__restrict__ bt = multi_batches(table);
+    const DevMphf *__restrict__ mp = multi_mphfs(table);
     for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        // last descriptor whose first tile is <= t (uniform across the block)
+        // last batch whose first tile is <= t (uniform across the block)
         uint32_t lo = 0, hi = count - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) / 2;
-            if (d[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+            if (tb[mid] <= t) lo = mid; else hi = mid - 1;
         }
-        const MultiDesc &q = d[lo];
-        const uint64_t base = (t - q.tile_begin) * (uint64_t)tile + threadIdx.x;
-        if (q.bytes) {
-            if (q.out64)
-                process_tile<K, uint64_t, true>(q.m, nullptr, q.data, q.offsets, q.nq, static_cast<uint64_t *>(q.out),
-                                                base, blockDim.x);
+        const MultiBatch &q = bt[lo];
+        const DevMphf &m = mp[q.mphf];
+        const uint64_t base = (t - tb[lo]) * (uint64_t)tile + threadIdx.x;
+        if (q.flags & kBatchBytes) {
+            const uint8_t *data = static_cast<const uint8_t *>(q.keys);
+            if (q.flags & kBatchOut64)
+                process_tile<K, uint64_t, true>(m, nullptr, data, q.offsets, q.nq, static_cast<uint64_t *>(q.out), base,
+                                                blockDim.x);
             else
-                process_tile<K, uint32_t, true>(q.m, nullptr, q.data, q.offsets, q.nq, static_cast<uint32_t *>(q.out),
-                                                base, blockDim.x);
+                process_tile<K, uint32_t, true>(m, nullptr, data, q.offsets, q.nq, static_cast<uint32_t *>(q.out), base,
+                                                blockDim.x);
         } else {
-            if (q.out64)
-                process_tile<K, uint64_t, false>(q.m, q.keys, nullptr, nullptr, q.nq, static_cast<uint64_t *>(q.out),
-                                                 base, blockDim.x);
+            const uint64_t *keys = static_cast<const uint64_t *>(q.keys);
+            if (q.flags & kBatchOut64)
+                process_tile<K, uint64_t, false>(m, keys, nullptr, nullptr, q.nq, static_cast<uint64_t *>(q.out), base,
+                                                 blockDim.x);
             else
-                process_tile<K, uint32_t, false>(q.m, q.keys, nullptr, nullptr, q.nq, static_cast<uint32_t *>(q.out),
-                                                 base, blockDim.x);
+                process_tile<K, uint32_t, false>(m, keys, nullptr, nullptr, q.nq, static_cast<uint32_t *>(q.out), base,
+                                                 blockDim.x);
         }
     }
 }

@@ -423,7 +423,7 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
             break;
         }
         if (zc) {
-            if (hipHostMalloc(&s.h_table, ptrhash::multi_table_bytes(cfg->max_batches), pin) != hipSuccess ||
+            if (hipHostMalloc(&s.h_table, ptrhash::multi_table_capacity(cfg->max_batches), pin) != hipSuccess ||
                 hipHostGetDevicePointer((void **)&s.v_table, s.h_table, 0) != hipSuccess ||
                 hipHostGetDevicePointer((void **)&s.v_keys, s.h_keys, 0) != hipSuccess ||
                 hipHostGetDevicePointer((void **)&s.v_out, s.h_out, 0) != hipSuccess) {
