@@ -1,0 +1,102 @@
+"""Host-side logic of the measurement path: bench.py's refusal of more than
+one GPU, the profile lookups it reports from, and profsum's counter
+arithmetic on a small synthetic rocprofv3 database."""
+import json
+import os
+import sqlite3
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2502_15539_amd import profsum  # noqa: E402
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_workload_table_names_every_runner():
+    kinds = {w[1] for w in bench.WORKLOADS.values()}
+    assert kinds == {"u64", "cached", "bytes", "multi", "serve"}
+    assert bench.WORKLOADS["u64_1e9"][0] == 10**9
+
+
+def test_valu_peak_from_unit_counts():
+    # 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
+    assert bench.VALU_PEAK_GINSTS == pytest.approx(614.4)
+    # x 64 lanes x 2 (FMA) x 2 (dual issue) = the published fp32 vector peak
+    assert bench.VALU_PEAK_GINSTS * 64 * 2 * 2 / 1000 == pytest.approx(157.3, rel=1e-3)
+
+
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("// header\nint f(int x) { return x + 1; }  // trailing\n/* block\n comment */\n")
+    monkeypatch.setattr(profsum, "HERE", str(tmp_path))
+    monkeypatch.setattr(profsum, "KERNEL_SOURCES", ["k.hip"])
+    h0 = profsum.kernel_source_hash()
+    src.write_text("// another header\n\nint f(int x) { return x + 1; }\n")
+    assert profsum.kernel_source_hash() == h0
+    src.write_text("int f(int x) { return x + 2; }\n")
+    assert profsum.kernel_source_hash() != h0
+
+
+def _fake_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_traffic_scales_by_the_copy_kernel(tmp_path):
+    # copy kernel: 8e9 bytes each way, counted as half the read bytes
+    fetch = tmp_path / "f.db"
+    write = tmp_path / "w.db"
+    _fake_db(fetch, [("ptrhash::bench_copy_k<1>(...)", "FETCH_SIZE", 4e9 / 1024),
+                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "FETCH_SIZE", 60e9 / 1024),
+                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "FETCH_SIZE", 62e9 / 1024)])
+    _fake_db(write, [("ptrhash::bench_copy_k<1>(...)", "WRITE_SIZE", 8e9 / 1024),
+                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "WRITE_SIZE", 8e9 / 1024)])
+    out = tmp_path / "t.json"
+    args = type("A", (), {"fetch": str(fetch), "write": str(write), "kernel": "query_pipelined<1, unsigned long>",
+                          "copy": "bench_copy_k<1>", "copy_bytes": 8e9, "scale_from": None, "out": str(out)})
+    res = profsum.traffic(args)
+    assert res["fetch_scale"] == pytest.approx(2.0)
+    assert res["write_scale"] == pytest.approx(1.0)
+    assert res["fetch_bytes"] == pytest.approx(122e9)  # mean of the two dispatches, doubled
+    assert res["traffic_bytes_per_launch"] == pytest.approx(130e9)
+    assert json.load(open(out))["kernel_source_sha256"] == profsum.kernel_source_hash()
+
+
+def test_profile_lookups_report_only_matching_profiles(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("w", 10.0, 10**6) == (None, None)
+    roof = bench.profiled_valu("w", 10.0, "query_pipelined<8, unsigned int>")
+    assert roof["bound"] == "alu" and roof["achieved"] is None
+
+    good = profsum.kernel_source_hash()
+    json.dump({"traffic_bytes_per_launch": 1e9, "fetch_scale": 2.0, "write_scale": 1.0,
+               "kernel_source_sha256": good}, open(tmp_path / "profiles" / "traffic_w.json", "w"))
+    b, info = bench.profiled_traffic("w", 10.0, 10**6)
+    assert b == 1e9 and info["traffic_GBps"] == pytest.approx(100.0)
+    json.dump({"traffic_bytes_per_launch": 1e9, "kernel_source_sha256": "stale"},
+              open(tmp_path / "profiles" / "traffic_w.json", "w"))
+    assert bench.profiled_traffic("w", 10.0, 10**6)[0] is None
+
+    json.dump({"kernel": "query_pipelined<8, unsigned int>", "valu_insts_per_launch": 6.144e9, "valu_busy_pct": 90.0,
+               "valu_utilization_pct": 70.0, "kernel_source_sha256": good},
+              open(tmp_path / "profiles" / "valu_w.json", "w"))
+    roof = bench.profiled_valu("w", 10.0, "query_pipelined<8, unsigned int>")
+    assert roof["achieved"] == pytest.approx(614.4) and roof["frac"] == pytest.approx(1.0)
+    roof = bench.profiled_valu("w", 10.0, "query_pipelined<4, unsigned int>")  # another shape: not comparable
+    assert roof["achieved"] is None and roof["profiled_kernel"] == "query_pipelined<8, unsigned int>"
