@@ -64,6 +64,9 @@ WORKLOADS = {
                                  "keys, Default params, the single-part ones with the x mod S reduce; batch sizes "
                                  "log-uniform in [1, 65536], 24.1M member keys drawn with replacement), resident in "
                                  "HBM, all answered by one multi-MPHF launch per step"),
+    "bytes_3e8_h128": (3 * 10**8, "bytes", 32, "as bytes_3e8, with the 128-bit string hash that the parameter rule "
+                                               "takes beyond 2^32 keys (high half: part and bucket, low half: "
+                                               "slot) forced on"),
     "serve_c5": (0, "serve", 32, "64 resident MPHFs, n log-uniform in [1e4, 1e7] u64 keys, Default params (the "
                                  "23 that get one part use the x mod S reduce); "
                                  "Poisson arrivals of batches log-uniform in [1, 65536] keys, each against one "
@@ -294,6 +297,7 @@ def oracle_baseline_bytes(args, p, built, qd, qo, out, n):
     offs = qo[:ns + 1].cpu().numpy().view(np.uint64)
     data = qd[:int(offs[-1]) + 64].cpu().numpy()
     op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    op.hash_bits = p.hash_bits or 64
     m = O.Mphf(op, built.pilots, None, built.remap, None)
 
     def run(lo, hi):
@@ -471,7 +475,11 @@ def run_bytes(args, torch, K, P):
     d_data, d_off = P.gen_strings(n, K.KEY_SEED)
     torch.cuda.synchronize()
     t1 = time.time()
-    built = P.build_bytes_device(d_data, d_off, index_bits=bits, threads=threads)
+    params = None
+    if args.workload.endswith("_h128"):
+        params = P.params_default(n, P.PRESET_DEFAULT, key_kind=P.KEY_BYTES, index_bits=bits)
+        params.hash_bits = 128  # the device search takes 64-bit hashes only: this one searches on the host
+    built = P.build_bytes_device(d_data, d_off, params=params, index_bits=bits, threads=threads)
     t2 = time.time()
     total_bytes = int(d_off[-1].item())
     del d_data, d_off
@@ -499,6 +507,7 @@ def run_bytes(args, torch, K, P):
                  parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
                  build_search=built.placement,
                  paper_cpu_context_ns_per_key={"default_clef_loop": 37, "default_clef_stream": 23})
+    rec["config"]["hash_bits"] = p.hash_bits or 64
     rec["metric"] = "queries/s (ns/key) at n=3e8 byte-string keys"
     return rec, bij and (cpu is None or cpu["matches_gpu"])
 
