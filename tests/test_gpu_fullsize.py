@@ -18,6 +18,11 @@ library's host construction at 10^8 keys). The checks here:
   gives exactly the GPU's indices. The sampled keys are regenerated on the
   host from the seeded generators, not read back from the device;
 * non-members: 2^20 of them, every output equal to the oracle's.
+
+The 64-MPHF workload runs at its full size too: 4096 requests (24.1 M keys)
+in one multi-MPHF launch with the autotuner's shape, and 2000 of them
+through the server, every index equal to the oracle's query of the
+request's own MPHF.
 """
 import sys
 
@@ -28,6 +33,7 @@ from oracle import oracle as O
 from paper_2502_15539_amd import autotune
 from paper_2502_15539_amd import keygen as K
 from paper_2502_15539_amd import ptrhash as P
+from paper_2502_15539_amd import serving
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -186,3 +192,43 @@ def test_u64_beyond_2_32_keys():
     ref = O.query_u64(oracle_of(built), qs, O.REMAP_CLEF)
     assert np.array_equal(got, ref)
     assert int(ref.max()) >= 2**32  # the sample reaches indices beyond 32 bits
+
+
+def oracle_of_params(b):
+    p = b.params
+    if p.reduce_kind == P.REDUCE_MOD:
+        op = O.params_single_mod(p.n, S=p.slots, B=p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    else:
+        op = O.params_explicit(p.n, p.num_parts, p.log2_slots, p.buckets_per_part, gamma=p.gamma, seed=p.seed)
+    return O.Mphf(op, b.pilots, None, b.remap, None)
+
+
+def test_multi_mphf_fleet_full_size():
+    """64 MPHFs (n log-uniform in [1e4, 1e7]), 4096 requests of log-uniform
+    sizes in [1, 65536]: one tuned multi-MPHF launch, then 2000 requests
+    through the zero-copy server; every index equals the oracle's."""
+    say("[fullsize] serving fleet: 64 MPHFs")
+    fleet = serving.build_fleet(threads=16, log=say)
+    reqs, js = serving.make_requests(fleet, P.multi_max(), with_index=True)
+    oracles = [oracle_of_params(b) for _, _, b in fleet]
+    want = [O.query_u64(oracles[j], q, O.REMAP_CLEF) for (_, q, _), j in zip(reqs, js)]
+    dev = [(m, torch.from_numpy(q.view(np.int64)).to(DEV), torch.empty(len(q), dtype=torch.int32, device=DEV))
+           for m, q, _ in reqs]
+    say(f"[fullsize] multi launch over {len(dev)} requests, {sum(len(q) for _, q, _ in reqs)} keys")
+    plan = P.MultiPlan(len(dev))
+    shape, _ = autotune.tune_multi(torch, plan, dev, use_cache=False)
+    say(f"[fullsize] multi shape {shape}")
+    plan.launch()
+    torch.cuda.synchronize()
+    for (_, _, o), w in zip(dev, want):
+        assert np.array_equal(o.cpu().numpy().view(np.uint32).astype(np.uint64), w)
+    plan.close()
+
+    say("[fullsize] 2000 requests through the server")
+    srv = P.Server(streams=2, max_batches=1024, slot_keys=1 << 22, zero_copy=1, multi_kernel=shape)
+    tickets = [srv.submit(m, q, out) for m, q, out in reqs[:2000]]
+    for t in tickets:
+        srv.wait(t)
+    srv.close()
+    for (_, _, out), w in zip(reqs[:2000], want):
+        assert np.array_equal(out.astype(np.uint64), w)
