@@ -187,6 +187,21 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _device_tensor(t, name: str, itemsize: int, count: int):
+    """A contiguous device tensor with at least count elements of itemsize
+    bytes: the kernels write and read exactly that much, so a smaller or
+    wider buffer is refused here rather than overrun on the device."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.element_size() != itemsize:
+        raise ValueError(f"{name} must have {itemsize}-byte elements, not {t.element_size()}")
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} elements, {count} are needed")
+    return C.c_void_p(t.data_ptr())
+
+
 def _stream(stream):
     """A HIP stream handle: explicit int, a torch stream, or torch's current one."""
     if isinstance(stream, int):
@@ -253,14 +268,14 @@ def build_u64_device(keys, params: Params | None = None, threads: int = 0, strea
     info = BuildInfo()
     if placement != "host":
         p = p0.copy()
-        rc = lib().ptrhash_build_u64_gpu(_dev_ptr(keys), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
+        rc = lib().ptrhash_build_u64_gpu(_device_tensor(keys, "keys", 8, n), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
                                          C.byref(info), _stream(stream))
         if rc == 0:
             return Built(p, pilots, remap, info, "device")
         if placement == "device" or rc != E_RANGE:
             _check(rc, "ptrhash_build_u64_gpu")
     p = p0.copy()
-    _check(lib().ptrhash_build_u64_device(_dev_ptr(keys), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
+    _check(lib().ptrhash_build_u64_device(_device_tensor(keys, "keys", 8, n), n, C.byref(p), _np_ptr(pilots), _np_ptr(remap),
                                           int(threads), C.byref(info), _stream(stream)), "ptrhash_build_u64_device")
     return Built(p, pilots, remap, info, "host")
 
@@ -294,7 +309,7 @@ def build_bytes_device(data, offsets, params: Params | None = None, threads: int
     info = BuildInfo()
     if placement != "host":
         p = p0.copy()
-        rc = lib().ptrhash_build_bytes_gpu(_dev_ptr(data), _dev_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
+        rc = lib().ptrhash_build_bytes_gpu(_device_tensor(data, "data", 1, 0), _device_tensor(offsets, "offsets", 8, n + 1), n, C.byref(p), _np_ptr(pilots),
                                            _np_ptr(remap), C.byref(info), _stream(stream))
         if rc == 0:
             return Built(p, pilots, remap, info, "device")
@@ -312,6 +327,7 @@ class Mphf:
         h = C.c_void_p()
         _check(lib().ptrhash_create(C.byref(h)), "ptrhash_create")
         self._h = h
+        self.index_bytes = 0  # set by load
 
     def close(self):
         if self._h:
@@ -332,6 +348,7 @@ class Mphf:
         pilots = np.ascontiguousarray(pilots, dtype=np.uint8)
         remap = None if remap is None else np.ascontiguousarray(remap, dtype=np.uint8)
         _check(lib().ptrhash_load(self._h, _np_ptr(pilots), _np_ptr(remap), C.byref(params)), "ptrhash_load")
+        self.index_bytes = params.index_bits // 8  # output element size, checked on every query
         return self
 
     @classmethod
@@ -356,7 +373,9 @@ class Mphf:
     def query_into(self, keys, out, stream=None):
         """keys: cuda uint64 tensor; out: cuda tensor of index_bits width."""
         n = keys.numel()
-        _check(lib().ptrhash_query(self._h, _dev_ptr(keys), n, _dev_ptr(out), _stream(stream)), "ptrhash_query")
+        ob = self.index_bytes
+        _check(lib().ptrhash_query(self._h, _device_tensor(keys, "keys", 8, n), n, _device_tensor(out, "out", ob, n),
+                                   _stream(stream)), "ptrhash_query")
         return out
 
     def query(self, keys, stream=None):
@@ -367,9 +386,16 @@ class Mphf:
         return self.query_into(keys, out, stream)
 
     def query_bytes_into(self, data, offsets, out, stream=None):
+        """data: cuda uint8 tensor of packed strings (8-byte aligned, 64 readable
+        bytes after the last string); offsets: n + 1 u64 offsets; out: n
+        indices of index_bits width."""
         n = offsets.numel() - 1
-        _check(lib().ptrhash_query_bytes(self._h, _dev_ptr(data), _dev_ptr(offsets), n, _dev_ptr(out),
-                                         _stream(stream)), "ptrhash_query_bytes")
+        if n < 0:
+            raise ValueError("offsets needs at least one entry")
+        ob = self.index_bytes
+        _check(lib().ptrhash_query_bytes(self._h, _device_tensor(data, "data", 1, 0),
+                                         _device_tensor(offsets, "offsets", 8, n + 1), n,
+                                         _device_tensor(out, "out", ob, n), _stream(stream)), "ptrhash_query_bytes")
         return out
 
     def query_bytes(self, data, offsets, stream=None):
@@ -381,39 +407,44 @@ class Mphf:
 
 
 def bench_gather(keys, table, out, keys_per_lane=4, block=256, blocks_per_cu=0, stream=None):
-    _check(lib().ptrhash_bench_gather(_dev_ptr(keys), keys.numel(), _dev_ptr(table), table.numel(), _dev_ptr(out),
-                                      int(keys_per_lane), int(block), int(blocks_per_cu), _stream(stream)),
-           "ptrhash_bench_gather")
+    n = keys.numel()
+    _check(lib().ptrhash_bench_gather(_device_tensor(keys, "keys", 8, n), n, _device_tensor(table, "table", 1, 1),
+                                      table.numel(), _device_tensor(out, "out", 8, n), int(keys_per_lane), int(block),
+                                      int(blocks_per_cu), _stream(stream)), "ptrhash_bench_gather")
 
 
 def bench_gather_pure(n, table, sink, stream=None):
     """sink: int32 cuda tensor, its length (a multiple of 256) = lanes."""
-    _check(lib().ptrhash_bench_gather_pure(int(n), _dev_ptr(table), table.numel(), _dev_ptr(sink), sink.numel(),
-                                           _stream(stream)), "ptrhash_bench_gather_pure")
+    _check(lib().ptrhash_bench_gather_pure(int(n), _device_tensor(table, "table", 1, 1), table.numel(),
+                                           _device_tensor(sink, "sink", 4, 0), sink.numel(), _stream(stream)),
+           "ptrhash_bench_gather_pure")
 
 
 def bench_gather_pair(n, table, sink, xor_dist, stream=None):
     """Pure gather plus a second byte at o ^ xor_dist of each random offset o."""
-    _check(lib().ptrhash_bench_gather_pair(int(n), _dev_ptr(table), table.numel(), _dev_ptr(sink), sink.numel(),
-                                           int(xor_dist), _stream(stream)), "ptrhash_bench_gather_pair")
+    _check(lib().ptrhash_bench_gather_pair(int(n), _device_tensor(table, "table", 1, 1), table.numel(),
+                                           _device_tensor(sink, "sink", 4, 0), sink.numel(), int(xor_dist),
+                                           _stream(stream)), "ptrhash_bench_gather_pair")
 
 
 def bench_copy(keys, out, keys_per_lane=4, block=256, stream=None):
-    _check(lib().ptrhash_bench_copy(_dev_ptr(keys), keys.numel(), _dev_ptr(out), int(keys_per_lane), int(block),
-                                    _stream(stream)), "ptrhash_bench_copy")
+    n = keys.numel()
+    _check(lib().ptrhash_bench_copy(_device_tensor(keys, "keys", 8, n), n, _device_tensor(out, "out", 8, n),
+                                    int(keys_per_lane), int(block), _stream(stream)), "ptrhash_bench_copy")
 
 
 def gen_u64_keys(out, seed, start=0, stream=None):
     """Fill the cuda uint64 tensor ``out`` with keys start.. of the key set."""
-    _check(lib().ptrhash_gen_u64_keys(int(seed), int(start), out.numel(), _dev_ptr(out), _stream(stream)),
-           "ptrhash_gen_u64_keys")
+    _check(lib().ptrhash_gen_u64_keys(int(seed), int(start), out.numel(), _device_tensor(out, "out", 8, 0),
+                                      _stream(stream)), "ptrhash_gen_u64_keys")
     return out
 
 
 def gen_query_stream(out, n, key_seed, order_seed, start=0, stream=None):
     """Fill ``out`` with entries start.. of the shuffled member stream of the n-key set."""
     _check(lib().ptrhash_gen_query_stream(int(n), int(key_seed), int(order_seed), int(start), out.numel(),
-                                          _dev_ptr(out), _stream(stream)), "ptrhash_gen_query_stream")
+                                          _device_tensor(out, "out", 8, 0), _stream(stream)),
+           "ptrhash_gen_query_stream")
     return out
 
 
@@ -425,10 +456,15 @@ def make_descs(batches):
         d.handle = m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle
         if isinstance(keys, tuple):
             data, offsets = keys
-            d.data, d.offsets, d.n_q = data.data_ptr(), offsets.data_ptr(), offsets.numel() - 1
+            d.n_q = offsets.numel() - 1
+            d.data = _device_tensor(data, "data", 1, 0).value
+            d.offsets = _device_tensor(offsets, "offsets", 8, d.n_q + 1).value
         else:
-            d.keys, d.n_q = keys.data_ptr(), keys.numel()
-        d.out = out.data_ptr() if out is not None else None
+            d.n_q = keys.numel()
+            d.keys = _device_tensor(keys, "keys", 8, d.n_q).value
+        if out is not None and d.n_q:
+            # an unloaded handle (index_bytes 0) is left for the library to refuse
+            d.out = (_device_tensor(out, "out", m.index_bytes, d.n_q) if m.index_bytes else _dev_ptr(out)).value
     return arr
 
 
@@ -555,8 +591,8 @@ class Server:
         return t.value
 
     def submit_mapped(self, mphf: "Mphf", keys: np.ndarray, out: np.ndarray) -> int:
-        """As submit, with keys and out inside host_empty() memory: the
-        kernel reads and writes them in place (no host copies)."""
+        """As submit, with keys and out inside a HostBuffer (ptrhash_host_alloc
+        memory): the kernel reads and writes them in place (no host copies)."""
         assert keys.dtype == np.uint64 and keys.flags.c_contiguous and out.flags.c_contiguous
         want = np.uint64 if mphf.params.index_bits == 64 else np.uint32
         if out.dtype != want or len(out) < len(keys):
@@ -573,7 +609,7 @@ class Server:
 
     def replay(self, reqs, mapped=False) -> float:
         """reqs: list of (Mphf, keys ndarray, out ndarray, arrival_us);
-        mapped: the arrays are inside host_empty() memory."""
+        mapped: the arrays are inside a HostBuffer."""
         arr = (ServerRequest * max(1, len(reqs)))()
         for i, (m, k, o, t) in enumerate(reqs):
             arr[i].handle = m.handle.value if isinstance(m.handle, C.c_void_p) else m.handle

@@ -1,6 +1,7 @@
 """Host-side logic of the measurement path: bench.py's refusal of more than
-one GPU, the profile lookups it reports from, and profsum's counter
-arithmetic on a small synthetic rocprofv3 database."""
+one GPU, the profile lookups it reports from, profsum's counter arithmetic
+on a small synthetic rocprofv3 database, and the binding's refusal of
+device buffers that a kernel would overrun."""
 import json
 import os
 import sqlite3
@@ -100,3 +101,36 @@ def test_profile_lookups_report_only_matching_profiles(tmp_path, monkeypatch):
     assert roof["achieved"] == pytest.approx(614.4) and roof["frac"] == pytest.approx(1.0)
     roof = bench.profiled_valu("w", 10.0, "query_pipelined<4, unsigned int>")  # another shape: not comparable
     assert roof["achieved"] is None and roof["profiled_kernel"] == "query_pipelined<8, unsigned int>"
+
+
+class _FakeDeviceTensor:
+    """Stands in for a cuda tensor: the binding's checks read only these."""
+
+    def __init__(self, n, itemsize, contiguous=True, cuda=True):
+        self.is_cuda = cuda
+        self._n, self._size, self._contig = n, itemsize, contiguous
+
+    def is_contiguous(self):
+        return self._contig
+
+    def element_size(self):
+        return self._size
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_refuses_buffers_a_kernel_would_overrun():
+    from paper_2502_15539_amd import ptrhash as P
+
+    ok = P._device_tensor(_FakeDeviceTensor(10, 8), "keys", 8, 10)
+    assert ok.value == 4096
+    for t, msg in [(_FakeDeviceTensor(10, 8, cuda=False), "device"),
+                   (_FakeDeviceTensor(10, 8, contiguous=False), "contiguous"),
+                   (_FakeDeviceTensor(10, 4), "8-byte"),
+                   (_FakeDeviceTensor(9, 8), "10 are needed")]:
+        with pytest.raises(ValueError, match=msg):
+            P._device_tensor(t, "keys", 8, 10)

@@ -125,10 +125,17 @@ def test_multi_errors():
     with pytest.raises(P.PtrHashError) as e:
         P.query_multi([(g, q, None)])
     assert e.value.code == P.E_INVAL
+    o = torch.zeros(10, dtype=torch.int64 if g.index_bytes == 8 else torch.int32, device=DEV)
     plan = P.MultiPlan(2)
     with pytest.raises(P.PtrHashError) as e:
-        plan.set([(g, q, q)] * 3)
+        plan.set([(g, q, o)] * 3)
     assert e.value.code == P.E_RANGE
+    # an output of the wrong width or length is refused before any launch
+    wrong = torch.zeros(10, dtype=torch.int32 if g.index_bytes == 8 else torch.int64, device=DEV)
+    with pytest.raises(ValueError):
+        P.query_multi([(g, q, wrong)])
+    with pytest.raises(ValueError):
+        P.query_multi([(g, q, o[:5])])
     P.query_multi([])  # nothing to do
 
 
