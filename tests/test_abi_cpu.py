@@ -248,3 +248,15 @@ def test_device_string_build_rejects_bad_arguments_before_any_device_call():
     q = P.params_default(1000)  # u64-key params
     assert f(C.c_void_p(64), C.c_void_p(64), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None,
              None) == P.E_INVAL
+
+
+def test_builder_equals_oracle_one_huge_bucket():
+    """All 2100 keys in one bucket (one part of 2^20 slots): the host search
+    places it like the oracle (the device search stops at 2048 keys)."""
+    n = 2100
+    keys = K.u64_keys(n, seed=21)
+    m = O.build_u64(keys, params=O.params_explicit(n, 1, 20, 1))
+    b = P.build_u64(keys, params=lib_params(m, P.REMAP_CLEF, 32), threads=2)
+    assert b.info.max_bucket_size == n == m.stats.max_bucket_size
+    assert b.params.seed == m.params.seed
+    assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)

@@ -113,6 +113,24 @@ def test_device_search_errors():
     assert b.placement == "host"
 
 
+def test_device_search_bucket_limit_falls_back_to_host():
+    """One bucket of 2100 keys (over the device search's 2048-key limit):
+    the device search refuses it with E_RANGE before any launch, and the
+    automatic placement builds it on the host, equal to the oracle."""
+    n = 2100
+    keys = K.u64_keys(n, seed=21)
+    m = O.build_u64(keys, params=O.params_explicit(n, 1, 20, 1))
+    q = lib_params(m, P.REMAP_CLEF, 32)
+    say(f"[gpu-build] one bucket of {n} keys")
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_u64_device(dev(keys), params=q, placement="device")
+    assert e.value.code == P.E_RANGE
+    b = P.build_u64_device(dev(keys), params=q, placement="auto")
+    assert b.placement == "host" and b.info.max_bucket_size == n
+    assert b.params.seed == m.params.seed
+    assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
+
+
 def test_device_search_equals_host_search_1e8():
     n = 10**8
     say(f"[gpu-build] n={n}: device keys, device search vs host search")
