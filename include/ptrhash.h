@@ -243,8 +243,9 @@ typedef struct ptrhash_server_metrics {
     uint64_t launches;    /* multi-MPHF launches */
     uint64_t keys;        /* keys answered */
     uint64_t queued;      /* requests waiting for a slot now */
-    double p50_us, p99_us, max_us;  /* submit -> indices delivered */
-    double wait_p50_us, wait_p99_us; /* submit -> launch enqueued (queueing + copy-in) */
+    double p50_us, p99_us, max_us;  /* submit -> indices delivered, over the most recent
+                                       2^20 requests completed since the last reset */
+    double wait_p50_us, wait_p99_us; /* submit -> launch enqueued (queueing + copy-in), same window */
 } ptrhash_server_metrics;
 
 /* One request of a replayed arrival schedule (host keys and output). */

@@ -168,6 +168,27 @@ void add_copy(std::vector<CopyPool::Job> &jobs, void *dst, const void *src, size
                         std::min(kChunk, bytes - o)});
 }
 
+// The most recent kStatWindow samples (a ring once full), so that a server
+// that runs for hours keeps bounded memory and its percentiles describe
+// recent traffic.
+constexpr size_t kStatWindow = size_t(1) << 20;
+struct StatWindow {
+    std::vector<double> v;
+    size_t next = 0;
+    void add(double x) {
+        if (v.size() < kStatWindow) {
+            v.push_back(x);
+        } else {
+            v[next] = x;
+            next = (next + 1) % kStatWindow;
+        }
+    }
+    void clear() {
+        v.clear();
+        next = 0;
+    }
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -194,8 +215,8 @@ struct ptrhash_server {
     uint64_t next_ticket = 1;
     std::unordered_set<uint64_t> outstanding;       // submitted, not finished
     std::unordered_map<uint64_t, double> finished;  // ticket -> latency (us), until waited for
-    std::vector<double> latencies;                   // all completed requests
-    std::vector<double> waits;                       // submit -> launch enqueued
+    StatWindow latencies;                            // completed requests (recent ones)
+    StatWindow waits;                                // submit -> launch enqueued
     CopyPool *pool = nullptr;
     uint64_t launches = 0, completed = 0, keys_done = 0;
     int error = PTRHASH_OK;
@@ -233,11 +254,11 @@ void retire(ptrhash_server *srv, Slot &s) {
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lock(srv->mu);
     for (const Request &r : s.reqs) {
-        srv->waits.push_back(std::chrono::duration<double, std::micro>(r.t_launch - r.t_submit).count());
+        srv->waits.add(std::chrono::duration<double, std::micro>(r.t_launch - r.t_submit).count());
         const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
         srv->outstanding.erase(r.ticket);
         srv->finished[r.ticket] = us;
-        srv->latencies.push_back(us);
+        srv->latencies.add(us);
         srv->completed++;
         srv->keys_done += r.n_q;
     }
@@ -486,7 +507,7 @@ static int submit_at(ptrhash_server *srv, ptrhash_handle *h, const uint64_t *key
     if (n_q == 0) {
         srv->finished[r.ticket] = 0.0;
         srv->completed++;
-        srv->latencies.push_back(0.0);
+        srv->latencies.add(0.0);
         srv->cv_done.notify_all();
         return PTRHASH_OK;
     }
@@ -561,13 +582,13 @@ PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics
     st->launches = srv->launches;
     st->keys = srv->keys_done;
     st->queued = srv->queue.size();
-    std::vector<double> v(srv->latencies);
+    std::vector<double> v(srv->latencies.v);
     std::sort(v.begin(), v.end());
     auto pct = [&](double q) { return v.empty() ? 0.0 : v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
     st->p50_us = pct(0.50);
     st->p99_us = pct(0.99);
     st->max_us = v.empty() ? 0.0 : v.back();
-    std::vector<double> w(srv->waits);
+    std::vector<double> w(srv->waits.v);
     std::sort(w.begin(), w.end());
     auto wp = [&](double q) { return w.empty() ? 0.0 : w[std::min(w.size() - 1, (size_t)(q * (w.size() - 1) + 0.5))]; };
     st->wait_p50_us = wp(0.50);
