@@ -22,6 +22,12 @@
  *  - Queries are asynchronous on the caller's stream: arguments are checked
  *    on the host before the launch; a fault inside a kernel surfaces at the
  *    caller's next synchronisation of that stream.
+ *  - Threads: a loaded handle may be queried from several host threads and
+ *    streams at once (queries only read it). ptrhash_load, ptrhash_set_kernel,
+ *    ptrhash_set_occupancy and ptrhash_destroy change a handle and must not
+ *    overlap any other call on it. A multi plan is used by one thread at a
+ *    time; ptrhash_query_multi and the server calls other than
+ *    ptrhash_server_destroy may be made from any thread.
  */
 #ifndef PTRHASH_H
 #define PTRHASH_H
