@@ -338,6 +338,7 @@ def run_u64(args, torch, K, P):
     t1 = time.time()
     preset = {"u64_1e9_fast": P.PRESET_FAST, "u64_1e9_compact": P.PRESET_COMPACT}.get(args.workload,
                                                                                       P.PRESET_DEFAULT)
+    log(f"[bench] keygen {time.time() - t0:.1f}s; building the MPHF")
     built = P.build_u64_device(keys, index_bits=bits, threads=threads, preset=preset)
     t2 = time.time()
     del keys
