@@ -10,5 +10,6 @@ enum : uint32_t {
     kPlaceHeapFull = 2,  // more requeued buckets waiting than the LDS heap holds
     kPlaceTooLarge = 3,  // a bucket larger than the search handles
     kPlaceCorrupt = 4,   // a slot record failed its consistency check
+    kPlaceCancelled = 5, // stopped early: an earlier seed already succeeded
 };
 }  // namespace ptrhash

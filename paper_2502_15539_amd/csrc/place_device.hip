@@ -175,7 +175,15 @@ struct PlaceArgs {
     uint32_t *next_part;        // work counter, zeroed
     uint32_t *status;           // per part
     uint64_t *evictions;        // per part
+    uint32_t *cancel;           // set (by cancel_k) when this seed's result is no longer needed
 };
+
+// The cancel flag, read at agent scope so that a store from another stream's
+// kernel is seen; wave-uniform.
+__device__ __forceinline__ bool cancel_requested(uint32_t *flag) {
+    const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane((int)v) != 0;
+}
 
 // Pairwise distinctness of up to 64 slots, key j in lane j (j < s): lane a
 // compares with lane a+d mod 64 for d = 1..32, which covers every pair.
@@ -288,6 +296,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
     uint32_t *big = a.big + (uint64_t)blockIdx.x * kMaxBucket;
 
     for (;;) {
+        if (cancel_requested(a.cancel)) break;
         uint32_t p = 0;
         if (lane == 0) p = atomicAdd(a.next_part, 1u);
         p = (uint32_t)__builtin_amdgcn_readfirstlane((int)p);
@@ -311,6 +320,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
 
         for (uint64_t iter = 0;; ++iter) {
             if (iter > max_iter) { status = kPlaceFailed; break; }
+            if ((iter & 8191u) == 8191u && cancel_requested(a.cancel)) { status = kPlaceCancelled; break; }
             // next bucket: the larger of the order's head and the heap's top
             uint32_t s = 0, id = 0;
             bool from_order = false;
@@ -553,9 +563,11 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
 // ---------------------------------------------------------------------------
 // Host side: buffers, passes, reseeding.
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <thread>
 #include <vector>
 
 #include "builder.h"
@@ -625,9 +637,37 @@ __global__ void equal_pairs_k(const uint64_t *__restrict__ H, const uint64_t *__
         }
 }
 
+// Stop the search of a seed whose result is no longer needed (one lane, a
+// vector atomic at agent scope; runs on its own stream beside the search).
+__global__ void cancel_k(uint32_t *flag) {
+    if (threadIdx.x == 0) atomicExch(flag, 1u);
+}
+
+// The buffers of one seed's search. Slot 0 runs on the caller's stream; the
+// others, used when seeds run side by side, on streams of their own.
+struct Attempt {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t done = nullptr;
+    uint8_t *pil = nullptr;
+    uint32_t *taken = nullptr, *big = nullptr, *next = nullptr, *status = nullptr, *cancel = nullptr;
+    ptrhash::SlotRec *recs = nullptr;
+    uint64_t *ev = nullptr;
+    uint32_t *status_h = nullptr;  // pinned host copies, filled by the search's stream
+    uint64_t *ev_h = nullptr;
+    uint64_t seed = 0;
+    bool busy = false;
+    std::chrono::steady_clock::time_point started{};
+};
+
+constexpr int kSpecSlots = 4;  // seeds searched side by side at most
+
 // Device pilot search over one set of sorted 64-bit hashes: bucket starts,
 // the (size desc, id asc) order, the hashes in that order, then one search
-// kernel per seed.
+// kernel per seed. A seed whose search runs far longer than a normal one
+// (a part caught in an eviction cycle) has the following seeds started on
+// the CUs its finished parts left idle; the result is still the first seed
+// that succeeds, and later seeds still running then are cancelled.
 class GpuSearch {
   public:
     GpuSearch(const ptrhash_params *params, uint64_t n, hipStream_t stream) : n_(n), stream_(stream) {
@@ -690,13 +730,50 @@ class GpuSearch {
         HIP_OR_FAIL(buf_.get(&ka_, total_), "order keys");
         HIP_OR_FAIL(buf_.get(&kb_, total_), "order keys");
         HIP_OR_FAIL(buf_.get(&ostart_, total_), "order offsets");
-        HIP_OR_FAIL(buf_.get(&pil_, total_), "pilots");
-        HIP_OR_FAIL(buf_.get(&taken_, taken_words_), "taken bits");
-        HIP_OR_FAIL(buf_.get(&recs_, grid_ * S_), "slot records");
-        HIP_OR_FAIL(buf_.get(&big_, grid_ * (uint64_t)kMaxBucket), "bucket scratch");
-        HIP_OR_FAIL(buf_.get(&next_, 1), "work counter");
-        HIP_OR_FAIL(buf_.get(&status_, P_), "part status");
-        HIP_OR_FAIL(buf_.get(&ev_, P_), "part evictions");
+        att_.resize(kSpecSlots);
+        return alloc_attempt(att_[0], false);
+    }
+
+    ~GpuSearch() {
+        for (Attempt &t : att_) {
+            if (t.busy && t.done) (void)hipEventSynchronize(t.done);
+            if (t.done) (void)hipEventDestroy(t.done);
+            if (t.own_stream && t.stream) (void)hipStreamDestroy(t.stream);
+            if (t.status_h) (void)hipHostFree(t.status_h);
+            if (t.ev_h) (void)hipHostFree(t.ev_h);
+        }
+        if (ctrl_) (void)hipStreamDestroy(ctrl_);
+        if (prepared_) (void)hipEventDestroy(prepared_);
+    }
+
+    // Device bytes of one seed's search buffers.
+    uint64_t attempt_bytes() const {
+        return total_ + taken_words_ * 4 + grid_ * S_ * sizeof(ptrhash::SlotRec) + grid_ * (uint64_t)ptrhash::kMaxBucket * 4 +
+               P_ * 12 + 64;
+    }
+
+    // Buffers (and, for a side-by-side seed, a stream that first waits for
+    // the prepared order) of one search slot.
+    int alloc_attempt(Attempt &t, bool own_stream) {
+        using namespace ptrhash;
+        HIP_OR_FAIL(buf_.get(&t.pil, total_), "pilots");
+        HIP_OR_FAIL(buf_.get(&t.taken, taken_words_), "taken bits");
+        HIP_OR_FAIL(buf_.get(&t.recs, grid_ * S_), "slot records");
+        HIP_OR_FAIL(buf_.get(&t.big, grid_ * (uint64_t)kMaxBucket), "bucket scratch");
+        HIP_OR_FAIL(buf_.get(&t.next, 1), "work counter");
+        HIP_OR_FAIL(buf_.get(&t.cancel, 1), "cancel flag");
+        HIP_OR_FAIL(buf_.get(&t.status, P_), "part status");
+        HIP_OR_FAIL(buf_.get(&t.ev, P_), "part evictions");
+        HIP_OR_FAIL(hipHostMalloc(&t.status_h, P_ * sizeof(uint32_t), hipHostMallocDefault), "pinned status");
+        HIP_OR_FAIL(hipHostMalloc(&t.ev_h, P_ * sizeof(uint64_t), hipHostMallocDefault), "pinned evictions");
+        HIP_OR_FAIL(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "event");
+        if (own_stream) {
+            HIP_OR_FAIL(hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking), "stream");
+            t.own_stream = true;
+            HIP_OR_FAIL(hipStreamWaitEvent(t.stream, prepared_, 0), "stream wait");
+        } else {
+            t.stream = stream_;
+        }
         return PTRHASH_OK;
     }
 
@@ -784,19 +861,22 @@ class GpuSearch {
         hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream_, okeys_, ostart_, bst_, H, m_,
                            max_size_, size_bits_, id_bits_, OH);
         HIP_OR_FAIL(hipGetLastError(), "scatter launch");
+        if (!prepared_) HIP_OR_FAIL(hipEventCreateWithFlags(&prepared_, hipEventDisableTiming), "event");
+        HIP_OR_FAIL(hipEventRecord(prepared_, stream_), "event record");
         phase("order");
         return PTRHASH_OK;
     }
 
-    // One search with the given seed; *failed: some part failed (reseed).
-    int search(uint64_t seed, bool *failed) {
+    // Start the search of one seed on a slot (asynchronous).
+    int launch(Attempt &t, uint64_t seed) {
         using namespace ptrhash;
-        m_.seed = seed;
-        HIP_OR_FAIL(hipMemsetAsync(pil_, 0, total_, stream_), "memset");
-        HIP_OR_FAIL(hipMemsetAsync(taken_, 0, taken_words_ * sizeof(uint32_t), stream_), "memset");
-        HIP_OR_FAIL(hipMemsetAsync(next_, 0, sizeof(uint32_t), stream_), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(t.pil, 0, total_, t.stream), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(t.taken, 0, taken_words_ * sizeof(uint32_t), t.stream), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(t.next, 0, sizeof(uint32_t), t.stream), "memset");
+        HIP_OR_FAIL(hipMemsetAsync(t.cancel, 0, sizeof(uint32_t), t.stream), "memset");
         PlaceArgs a{};
         a.m = m_;
+        a.m.seed = seed;
         a.H = H_;
         a.bst = bst_;
         a.okeys = okeys_;
@@ -806,49 +886,182 @@ class GpuSearch {
         a.size_bits = size_bits_;
         a.id_bits = id_bits_;
         a.max_evictions = kEvictionFactor * S_;
-        a.pilots = pil_;
-        a.taken = taken_;
-        a.recs = recs_;
-        a.big = big_;
-        a.next_part = next_;
-        a.status = status_;
-        a.evictions = ev_;
+        a.pilots = t.pil;
+        a.taken = t.taken;
+        a.recs = t.recs;
+        a.big = t.big;
+        a.next_part = t.next;
+        a.status = t.status;
+        a.evictions = t.ev;
+        a.cancel = t.cancel;
         if (mod_)
-            hipLaunchKernelGGL(place_k<true>, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
+            hipLaunchKernelGGL(place_k<true>, dim3((uint32_t)grid_), dim3(kWave), lds_, t.stream, a);
         else
-            hipLaunchKernelGGL(place_k<false>, dim3((uint32_t)grid_), dim3(kWave), lds_, stream_, a);
+            hipLaunchKernelGGL(place_k<false>, dim3((uint32_t)grid_), dim3(kWave), lds_, t.stream, a);
         HIP_OR_FAIL(hipGetLastError(), "search launch");
-        status_h_.resize(P_);
-        ev_h_.resize(P_);
-        HIP_OR_FAIL(hipMemcpyAsync(status_h_.data(), status_, P_ * sizeof(uint32_t), hipMemcpyDeviceToHost, stream_),
+        HIP_OR_FAIL(hipMemcpyAsync(t.status_h, t.status, P_ * sizeof(uint32_t), hipMemcpyDeviceToHost, t.stream),
                     "copy out");
-        HIP_OR_FAIL(hipMemcpyAsync(ev_h_.data(), ev_, P_ * sizeof(uint64_t), hipMemcpyDeviceToHost, stream_),
-                    "copy out");
-        HIP_OR_FAIL(hipStreamSynchronize(stream_), "search");
+        HIP_OR_FAIL(hipMemcpyAsync(t.ev_h, t.ev, P_ * sizeof(uint64_t), hipMemcpyDeviceToHost, t.stream), "copy out");
+        HIP_OR_FAIL(hipEventRecord(t.done, t.stream), "event record");
+        t.seed = seed;
+        t.busy = true;
+        t.started = std::chrono::steady_clock::now();
+        return PTRHASH_OK;
+    }
+
+    // The outcome of a finished search; *failed: some part failed (reseed).
+    int check(Attempt &t, bool *failed) {
+        using namespace ptrhash;
+        t.busy = false;
         *failed = false;
         for (uint64_t p = 0; p < P_; ++p) {
-            if (status_h_[p] == kPlaceHeapFull || status_h_[p] == kPlaceTooLarge)
+            const uint32_t st = t.status_h[p];
+            if (st == kPlaceHeapFull || st == kPlaceTooLarge)
                 return set_error(PTRHASH_E_RANGE, "device placement: part %llu outside the search's limits (%u)",
-                                 (unsigned long long)p, status_h_[p]);
-            if (status_h_[p] > kPlaceTooLarge)
-                return set_error(PTRHASH_E_HIP, "device placement: inconsistent slot record in part %llu",
-                                 (unsigned long long)p);
-            *failed |= status_h_[p] != kPlaceOk;
+                                 (unsigned long long)p, st);
+            if (st != kPlaceOk && st != kPlaceFailed)
+                return set_error(PTRHASH_E_HIP, "device placement: part %llu ended with status %u",
+                                 (unsigned long long)p, st);
+            *failed |= st != kPlaceOk;
         }
+        return PTRHASH_OK;
+    }
+
+    // One search with the given seed on slot 0, waited for.
+    int search(uint64_t seed, bool *failed) {
+        using namespace ptrhash;
+        if (int rc = launch(att_[0], seed)) return rc;
+        HIP_OR_FAIL(hipEventSynchronize(att_[0].done), "search");
+        if (int rc = check(att_[0], failed)) return rc;
         phase("search");
         return PTRHASH_OK;
+    }
+
+    // Seconds after which a seed's search counts as stuck: three times a
+    // generous estimate of a normal search (rounds of parts x buckets x
+    // 1.5 us per placement) plus 2 s; PTRHASH_SPECULATE_MS overrides it.
+    double stuck_after() const {
+        if (const char *e = std::getenv("PTRHASH_SPECULATE_MS")) return std::atof(e) / 1e3;
+        const double rounds = (double)((P_ + grid_ - 1) / grid_);
+        return 2.0 + 3.0 * rounds * (double)B_ * 1.5e-6;
+    }
+
+    // Extra search slots that fit in free device memory (keeping 2 GiB and
+    // a tenth of it spare), allocated now; returns the slots in use.
+    int add_slots() {
+        size_t freeb = 0, totalb = 0;
+        if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return 1;
+        const uint64_t spare = std::max<uint64_t>(2ull << 30, freeb / 10);
+        int slots = 1;
+        uint64_t avail = freeb > spare ? freeb - spare : 0;
+        while (slots < kSpecSlots && avail >= attempt_bytes()) {
+            if (alloc_attempt(att_[slots], true) != PTRHASH_OK) {
+                (void)hipGetLastError();
+                break;
+            }
+            avail -= attempt_bytes();
+            ++slots;
+        }
+        if (!ctrl_ && slots > 1 && hipStreamCreateWithFlags(&ctrl_, hipStreamNonBlocking) != hipSuccess) return 1;
+        return slots;
+    }
+
+    // Cancel every running search but `keep` and wait for them to stop.
+    void cancel_others(const Attempt *keep) {
+        for (Attempt &t : att_)
+            if (t.busy && &t != keep && ctrl_) {
+                hipLaunchKernelGGL(cancel_k, dim3(1), dim3(64), 0, ctrl_, t.cancel);
+                (void)hipGetLastError();
+            }
+        for (Attempt &t : att_)
+            if (t.busy && &t != keep) {
+                (void)hipEventSynchronize(t.done);
+                t.busy = false;
+            }
+    }
+
+    // Seeds params->seed, +1, ... until one succeeds (at most kMaxSeeds).
+    int run_seeds(ptrhash_params *params, uint8_t *pilots, void *remap, ptrhash_build_info *info) {
+        using namespace ptrhash;
+        const uint64_t base = params->seed;
+        const double stuck = stuck_after();
+        int slot_of[kMaxSeeds];
+        for (int &x : slot_of) x = -1;
+        int slots = 1, next_seed = 1;
+        bool tried = false;  // side-by-side seeds tried (once)
+        if (int rc = launch(att_[0], base)) return rc;
+        slot_of[0] = 0;
+        for (int cur = 0; cur < kMaxSeeds; ++cur) {
+            Attempt &t = att_[slot_of[cur]];
+            for (;;) {
+                const hipError_t q = hipEventQuery(t.done);
+                if (q == hipSuccess) break;
+                if (q != hipErrorNotReady) {
+                    cancel_others(&t);
+                    return set_error(PTRHASH_E_HIP, "search: %s", hipGetErrorString(q));
+                }
+                const double ran = std::chrono::duration<double>(std::chrono::steady_clock::now() - t.started).count();
+                if (!tried && ran > stuck && next_seed < kMaxSeeds) {
+                    tried = true;
+                    slots = add_slots();
+                    for (int sl = 0; sl < slots && next_seed < kMaxSeeds; ++sl) {
+                        if (att_[sl].busy) continue;
+                        if (int rc = launch(att_[sl], base + (uint64_t)next_seed)) {
+                            cancel_others(nullptr);
+                            return rc;
+                        }
+                        slot_of[next_seed++] = sl;
+                    }
+                    if (timing_)
+                        std::fprintf(stderr, "[build] seed %d still searching after %.1f s: %d seeds side by side\n",
+                                     cur, ran, slots);
+                }
+                std::this_thread::sleep_for(std::chrono::milliseconds(1));
+            }
+            bool failed = false;
+            const int rc = check(t, &failed);
+            if (timing_)
+                std::fprintf(stderr, "[build] search seed %d %s after %.3f s\n", cur, rc ? "error" : failed ? "failed" : "ok",
+                             std::chrono::duration<double>(std::chrono::steady_clock::now() - t.started).count());
+            if (rc) {
+                cancel_others(nullptr);
+                return rc;
+            }
+            if (!failed) {
+                cancel_others(&t);
+                phase("search");
+                return finish(params, base + (uint64_t)cur, pilots, remap, info, (uint64_t)cur + 1, t);
+            }
+            // this slot is free again: the next seed not yet started goes there
+            const int want = slots == 1 ? cur + 1 : next_seed;
+            if (want < kMaxSeeds && slot_of[want] < 0) {
+                if (int rc2 = launch(t, base + (uint64_t)want)) {
+                    cancel_others(nullptr);
+                    return rc2;
+                }
+                slot_of[want] = (int)(&t - att_.data());
+                next_seed = want + 1;
+            }
+        }
+        cancel_others(nullptr);
+        if (info) *info = ptrhash_build_info{(uint64_t)kMaxSeeds, 0, 0, 0};
+        return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
     }
 
     // After a successful search: pilots and remap to the host, statistics.
     int finish(ptrhash_params *params, uint64_t seed, uint8_t *pilots, void *remap, ptrhash_build_info *info,
                uint64_t attempts) {
+        return finish(params, seed, pilots, remap, info, attempts, att_[0]);
+    }
+    int finish(ptrhash_params *params, uint64_t seed, uint8_t *pilots, void *remap, ptrhash_build_info *info,
+               uint64_t attempts, Attempt &t) {
         using namespace ptrhash;
         ptrhash_build_info local{};
         local.attempts = attempts;
         local.max_bucket_size = max_size_;
         for (uint64_t p = 0; p < P_; ++p) {
-            local.evictions += ev_h_[p];
-            local.max_part_evictions = std::max(local.max_part_evictions, ev_h_[p]);
+            local.evictions += t.ev_h[p];
+            local.max_part_evictions = std::max(local.max_part_evictions, t.ev_h[p]);
         }
         std::vector<uint64_t> taken;
         try {
@@ -856,11 +1069,11 @@ class GpuSearch {
         } catch (const std::bad_alloc &) {
             return set_error(PTRHASH_E_NOMEM, "host taken-slot bitvector");
         }
-        HIP_OR_FAIL(hipMemcpyAsync(pilots, pil_, total_, hipMemcpyDeviceToHost, stream_), "pilots to host");
-        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), taken_, taken_words_ * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                   stream_),
+        HIP_OR_FAIL(hipMemcpyAsync(pilots, t.pil, total_, hipMemcpyDeviceToHost, t.stream), "pilots to host");
+        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), t.taken, taken_words_ * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   t.stream),
                     "taken bits to host");
-        HIP_OR_FAIL(hipStreamSynchronize(stream_), "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(t.stream), "copy out");
         ptrhash_params out = *params;
         out.seed = seed;
         if (int rc = remap_from_taken(&out, taken, remap)) return rc;
@@ -885,16 +1098,13 @@ class GpuSearch {
     unsigned long long *maxes_ = nullptr;
     uint32_t *flags_ = nullptr;
     uint8_t *sort_temp_ = nullptr;
-    uint8_t *pil_ = nullptr;
-    uint32_t *taken_ = nullptr, *big_ = nullptr, *next_ = nullptr, *status_ = nullptr;
-    ptrhash::SlotRec *recs_ = nullptr;
-    uint64_t *ev_ = nullptr;
+    std::vector<Attempt> att_;
+    hipStream_t ctrl_ = nullptr;     // cancel kernels
+    hipEvent_t prepared_ = nullptr;  // the search order is ready
     const uint64_t *H_ = nullptr, *okeys_ = nullptr;
     uint64_t *OH_ = nullptr;
     uint64_t max_size_ = 0;
     uint32_t size_bits_ = 0, id_bits_ = 0;
-    std::vector<uint32_t> status_h_;
-    std::vector<uint64_t> ev_h_;
 };
 
 int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
@@ -918,14 +1128,8 @@ int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t 
     if (int rc = g.prepare(hdb.Current(), hdb.Alternate(), &dup, &overflow)) return rc;
     if (dup) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
     if (overflow) return set_error(PTRHASH_E_BUILD, "a part holds more than S keys");
-    for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
-        const uint64_t seed = params->seed + (uint64_t)attempt;
-        bool failed = false;
-        if (int rc = g.search(seed, &failed)) return rc;
-        if (!failed) return g.finish(params, seed, pilots, remap, info, (uint64_t)attempt + 1);
-    }
-    if (info) *info = ptrhash_build_info{(uint64_t)kMaxSeeds, 0, 0, 0};
-    return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
+    // the order does not depend on the seed: seeds may be searched side by side
+    return g.run_seeds(params, pilots, remap, info);
 }
 
 // Do two of the equal-hash pairs name the same string? (Then the keys are

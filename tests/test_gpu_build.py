@@ -94,6 +94,43 @@ def test_device_search_reseeds_like_oracle():
     assert b.info.attempts == m.stats.attempts
 
 
+# oracle attempts: 1, 1, 2, 3, 5, 9, and all 16 seeds failing
+@pytest.mark.parametrize("n,P_,log2,lam,kseed", [(20_000, 1, 15, 4.0, 4), (250_000, 1, 18, 3.5, 8),
+                                                  (30_000, 4, 13, 4.5, 20), (60_000, 8, 13, 4.5, 39),
+                                                  (30_000, 4, 13, 4.5, 33), (30_500, 4, 13, 4.5, 39),
+                                                  (30_000, 4, 13, 4.5, 38)])
+@pytest.mark.parametrize("stuck_ms", ["0", None])
+def test_side_by_side_seeds_equal_oracle(n, P_, log2, lam, kseed, stuck_ms, monkeypatch):
+    """With every search counted as stuck at once (PTRHASH_SPECULATE_MS=0)
+    up to four seeds are searched side by side and later ones cancelled when
+    an earlier one succeeds; without it, one seed after the other. Either
+    way the result must be the oracle's (same seed, pilots, remap and number
+    of attempts), whether seed 0 succeeds, several fail, or all do."""
+    if stuck_ms is None:
+        monkeypatch.delenv("PTRHASH_SPECULATE_MS", raising=False)  # one seed after the other
+    else:
+        monkeypatch.setenv("PTRHASH_SPECULATE_MS", stuck_ms)
+    keys = K.u64_keys(n, seed=kseed)
+    B = int(np.ceil(0.99 * (1 << log2) / lam))
+    o = O.params_explicit(n, P_, log2, B, seed=0)
+    say(f"[gpu-build] side by side n={n} P={P_} S=2^{log2} lambda={lam}")
+    try:
+        m = O.build_u64(keys, params=o)
+    except O.BuildError:
+        q = P.params_default(n)
+        q.num_parts, q.log2_slots, q.buckets_per_part, q.remap_len, q.seed = P_, log2, B, o.remap_len, 0
+        with pytest.raises(P.PtrHashError) as e:
+            P.build_u64_device(dev(keys), params=q, placement="device")
+        assert e.value.code == P.E_BUILD
+        return
+    p = lib_params(m)
+    p.seed = 0
+    b = P.build_u64_device(dev(keys), params=p, placement="device")
+    same(b, m)
+    assert b.info.attempts == m.stats.attempts
+    say(f"[gpu-build] attempts {b.info.attempts}")
+
+
 def test_device_search_errors():
     keys = K.u64_keys(5000, seed=3)
     keys[4000] = keys[12]
