@@ -479,7 +479,7 @@ def run_bytes(args, torch, K, P):
     params = None
     if args.workload.endswith("_h128"):
         params = P.params_default(n, P.PRESET_DEFAULT, key_kind=P.KEY_BYTES, index_bits=bits)
-        params.hash_bits = 128  # the device search takes 64-bit hashes only: this one searches on the host
+        params.hash_bits = 128
     built = P.build_bytes_device(d_data, d_off, params=params, index_bits=bits, threads=threads)
     t2 = time.time()
     total_bytes = int(d_off[-1].item())

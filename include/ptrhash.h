@@ -368,8 +368,14 @@ PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrha
  * gfx950), S a multiple of 32 when P > 1, buckets of at most 2048 keys;
  * outside them the call returns E_RANGE and ptrhash_build_u64_device
  * (host search) applies. Device memory: about 16*n + 33*P*B + P*S/8 bytes
- * plus 16*S bytes per compute unit, for the duration of the call. stream
- * orders the device work and is synchronised before return. Errors: E_INVAL,
+ * plus 16*S bytes per compute unit, for the duration of the call. A seed
+ * whose search runs three times longer than a normal one would (a part
+ * caught in an eviction cycle) has the next three seeds searched beside it
+ * on streams of the library's own, each with another P*B + P*S/8 + 16*S per
+ * compute unit of device memory when that much is free; seeds are still
+ * taken in order, so the result does not change (PTRHASH_SPECULATE_MS sets
+ * the threshold in ms). stream orders the device work and is synchronised
+ * before return. Errors: E_INVAL,
  * E_DUPLICATE, E_BUILD (a part with more than S keys, or 16 failed seeds),
  * E_RANGE, E_NOMEM, E_HIP. */
 PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
@@ -380,11 +386,14 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
  * readable bytes after the last string (the layout the query takes). The
  * string hash depends on the seed, so every attempt hashes and sorts again;
  * equal hashes of distinct strings cause a reseed, equal strings E_DUPLICATE,
- * like ptrhash_build_bytes (same result, byte for byte). 64-bit string
- * hashes only (E_RANGE for hash_bits = 128); E_RANGE also when more than 64
- * pairs of keys share a hash (the host construction examines them all).
- * Device memory: about 32*n + 33*P*B + P*S/8 bytes plus 16*S bytes per
- * compute unit. */
+ * like ptrhash_build_bytes (same result, byte for byte). With 128-bit
+ * hashes (hash_bits = 128) keys are sorted by the high half, which picks
+ * part and bucket, and the slots come from the low half; only keys equal in
+ * both halves collide. E_RANGE when more than 64 pairs of keys share a hash
+ * (the host construction examines them all) or, with 128-bit hashes, three
+ * keys share a high half. Device memory: about 32*n (48*n with 128-bit
+ * hashes) + 33*P*B + P*S/8 bytes plus 16*S bytes per compute unit. Seeds
+ * are searched one after the other. */
 PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
                                         ptrhash_params *params, uint8_t *pilots, void *remap,
                                         ptrhash_build_info *info, hipStream_t stream);

@@ -623,6 +623,44 @@ __global__ void hash_strings_gpu_k(const uint8_t *__restrict__ data, const uint6
     }
 }
 
+// 128-bit string hashes: hi (part and bucket) and lo (slot) of key i under
+// seed, ids[i] = i.
+__global__ void hash_strings128_gpu_k(const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets,
+                                      uint64_t n, uint64_t seed, uint64_t *__restrict__ hi, uint64_t *__restrict__ lo,
+                                      uint64_t *__restrict__ ids) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+        hi[i] = ptrhash::hash_bytes(seed, data, o0, o1 - o0, true, lo[i]);
+        ids[i] = i;
+    }
+}
+
+// out[i] = src[idx[i]]
+__global__ void gather_k(const uint64_t *__restrict__ src, const uint64_t *__restrict__ idx, uint64_t n,
+                         uint64_t *__restrict__ out) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = src[idx[i]];
+}
+
+// 128-bit hashes sorted by the high half: adjacent keys whose two halves
+// are both equal (count, and the first kMaxPairs as ids), and whether three
+// keys in a row share the high half (then not every equal pair is adjacent).
+__global__ void equal_pairs128_k(const uint64_t *__restrict__ hi, const uint64_t *__restrict__ lo,
+                                 const uint64_t *__restrict__ ids, uint64_t n, uint32_t *__restrict__ count,
+                                 uint64_t *__restrict__ pairs) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (hi[i] != hi[i - 1]) continue;
+        if (i >= 2 && hi[i - 2] == hi[i]) atomicOr(&count[1], 1u);
+        if (lo[i] == lo[i - 1]) {
+            const uint32_t k = atomicAdd(&count[0], 1u);
+            if (k < kMaxPairs) {
+                pairs[2 * k] = ids[i - 1];
+                pairs[2 * k + 1] = ids[i];
+            }
+        }
+    }
+}
+
 // Pairs of keys with equal hashes (adjacent after the sort): count them and
 // keep the first kMaxPairs (ids) for the host to compare.
 __global__ void equal_pairs_k(const uint64_t *__restrict__ H, const uint64_t *__restrict__ ids, uint64_t n,
@@ -802,9 +840,12 @@ class GpuSearch {
     // Bucket starts, order and ordered hashes for the sorted hashes H (OH: n
     // entries of scratch). *dup: two equal hashes; *overflow: a part with
     // more than S keys (then nothing else is prepared).
-    int prepare(const uint64_t *H, uint64_t *OH, bool *dup, bool *overflow) {
+    // Hs: the hashes the slots are computed from, in the order of H, when
+    // they differ from H (128-bit string hashes: H is the high half, which
+    // picks part and bucket, Hs the low half).
+    int prepare(const uint64_t *H, uint64_t *OH, bool *dup, bool *overflow, const uint64_t *Hs = nullptr) {
         using namespace ptrhash;
-        H_ = H;
+        H_ = Hs ? Hs : H;
         OH_ = OH;
         HIP_OR_FAIL(hipMemsetAsync(flags_, 0, sizeof(uint32_t), stream_), "memset");
         HIP_OR_FAIL(hipMemsetAsync(maxes_, 0, 2 * sizeof(unsigned long long), stream_), "memset");
@@ -858,7 +899,7 @@ class GpuSearch {
         }
         HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(sort_temp_, temp, osize, ostart_, (int64_t)total_, stream_),
                     "scan");
-        hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream_, okeys_, ostart_, bst_, H, m_,
+        hipLaunchKernelGGL(scatter_ordered_k, dim3(8192), dim3(256), 0, stream_, okeys_, ostart_, bst_, H_, m_,
                            max_size_, size_bits_, id_bits_, OH);
         HIP_OR_FAIL(hipGetLastError(), "scatter launch");
         if (!prepared_) HIP_OR_FAIL(hipEventCreateWithFlags(&prepared_, hipEventDisableTiming), "event");
@@ -1166,49 +1207,72 @@ int build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n, pt
     if (!data || !offsets || !params || !pilots) return set_error(PTRHASH_E_INVAL, "NULL argument");
     if (reinterpret_cast<uintptr_t>(data) & 7u) return set_error(PTRHASH_E_INVAL, "data must be 8-byte aligned");
     if (int rc = check_build_params(n, params, PTRHASH_KEY_BYTES)) return rc;
-    if (params->hash_bits == 128)
-        return set_error(PTRHASH_E_RANGE, "device construction takes 64-bit string hashes (n <= 2^32)");
     if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
+    // 128-bit hashes: the high half picks part and bucket, the low half the
+    // slot; two keys collide only when both halves are equal
+    const bool wide = params->hash_bits == 128;
     GpuSearch g(params, n, stream);
     if (int rc = g.init()) return rc;
     uint64_t *ha = nullptr, *hb = nullptr, *ia = nullptr, *ib = nullptr, *pairs = nullptr;
+    uint64_t *lo_raw = nullptr, *lo = nullptr;
     uint32_t *npairs = nullptr;
     HIP_OR_FAIL(g.buffers().get(&ha, n), "device hashes");
     HIP_OR_FAIL(g.buffers().get(&hb, n), "device hashes");
     HIP_OR_FAIL(g.buffers().get(&ia, n), "key ids");
     HIP_OR_FAIL(g.buffers().get(&ib, n), "key ids");
+    if (wide) {
+        HIP_OR_FAIL(g.buffers().get(&lo_raw, n), "device hashes");
+        HIP_OR_FAIL(g.buffers().get(&lo, n), "device hashes");
+    }
     HIP_OR_FAIL(g.buffers().get(&pairs, 2 * kMaxPairs), "pairs");
-    HIP_OR_FAIL(g.buffers().get(&npairs, 1), "pairs");
+    HIP_OR_FAIL(g.buffers().get(&npairs, 2), "pairs");
     std::vector<uint64_t> hpairs(2 * kMaxPairs);
     for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
         // the string hash depends on the seed: hash, sort and order per attempt
         const uint64_t seed = params->seed + (uint64_t)attempt;
-        hipLaunchKernelGGL(hash_strings_gpu_k, dim3(8192), dim3(256), 0, stream, data, offsets, n, seed, ha, ia);
+        if (wide)
+            hipLaunchKernelGGL(hash_strings128_gpu_k, dim3(8192), dim3(256), 0, stream, data, offsets, n, seed, ha,
+                               lo_raw, ia);
+        else
+            hipLaunchKernelGGL(hash_strings_gpu_k, dim3(8192), dim3(256), 0, stream, data, offsets, n, seed, ha, ia);
         HIP_OR_FAIL(hipGetLastError(), "hash launch");
         hipcub::DoubleBuffer<uint64_t> hdb(ha, hb), idb(ia, ib);
         if (int rc = g.sort(hdb, &idb)) return rc;
+        if (wide) {
+            hipLaunchKernelGGL(gather_k, dim3(8192), dim3(256), 0, stream, lo_raw, idb.Current(), n, lo);
+            HIP_OR_FAIL(hipGetLastError(), "gather launch");
+        }
         g.phase("hash+sort");
         bool dup = false, overflow = false;
         // the ids' second buffer serves as the ordered-hash scratch
-        if (int rc = g.prepare(hdb.Current(), idb.Alternate(), &dup, &overflow)) return rc;
+        if (int rc = g.prepare(hdb.Current(), idb.Alternate(), &dup, &overflow, wide ? lo : nullptr)) return rc;
         if (overflow) continue;  // a part with more than S keys: a new seed
-        if (dup) {
-            HIP_OR_FAIL(hipMemsetAsync(npairs, 0, sizeof(uint32_t), stream), "memset");
-            hipLaunchKernelGGL(equal_pairs_k, dim3(4096), dim3(256), 0, stream, hdb.Current(), idb.Current(), n,
-                               npairs, pairs);
+        if (dup) {  // equal (high halves of the) hashes
+            HIP_OR_FAIL(hipMemsetAsync(npairs, 0, 2 * sizeof(uint32_t), stream), "memset");
+            if (wide)
+                hipLaunchKernelGGL(equal_pairs128_k, dim3(4096), dim3(256), 0, stream, hdb.Current(), lo,
+                                   idb.Current(), n, npairs, pairs);
+            else
+                hipLaunchKernelGGL(equal_pairs_k, dim3(4096), dim3(256), 0, stream, hdb.Current(), idb.Current(), n,
+                                   npairs, pairs);
             HIP_OR_FAIL(hipGetLastError(), "pairs launch");
-            uint32_t np = 0;
-            HIP_OR_FAIL(hipMemcpyAsync(&np, npairs, sizeof np, hipMemcpyDeviceToHost, stream), "copy out");
+            uint32_t np[2] = {0, 0};
+            HIP_OR_FAIL(hipMemcpyAsync(np, npairs, sizeof np, hipMemcpyDeviceToHost, stream), "copy out");
             HIP_OR_FAIL(hipMemcpyAsync(hpairs.data(), pairs, hpairs.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                        stream),
                         "copy out");
             HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
-            bool same = false;
-            if (int rc = equal_strings(data, offsets, hpairs, np, stream, &same)) return rc;
-            if (same) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
-            if (np > kMaxPairs)  // more pairs than examined: the host construction checks them all
-                return set_error(PTRHASH_E_RANGE, "device construction: %u equal string hashes", np);
-            continue;  // distinct strings with one hash: a new seed
+            if (np[1])  // three equal high halves in a row: not every equal pair is adjacent
+                return set_error(PTRHASH_E_RANGE, "device construction: three keys share a 64-bit hash half");
+            if (np[0]) {
+                bool same = false;
+                if (int rc = equal_strings(data, offsets, hpairs, np[0], stream, &same)) return rc;
+                if (same) return set_error(PTRHASH_E_DUPLICATE, "two equal keys");
+                if (np[0] > kMaxPairs)  // more pairs than examined: the host construction checks them all
+                    return set_error(PTRHASH_E_RANGE, "device construction: %u equal string hashes", np[0]);
+                continue;  // distinct strings with one hash: a new seed
+            }
+            // 128-bit: equal high halves only; such keys share a bucket but not a slot hash
         }
         bool failed = false;
         if (int rc = g.search(seed, &failed)) return rc;

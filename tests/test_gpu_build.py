@@ -197,6 +197,26 @@ def test_device_string_build_equals_oracle(n):
     same(b, m)
 
 
+@pytest.mark.parametrize("n", [1, 7, 1000, 30_000, 300_000])
+def test_device_string_build_hash128_equals_oracle(n):
+    """128-bit string hashes (what the parameter rule takes beyond 2^32 keys):
+    part and bucket from the high half, the slot from the low half."""
+    data, off = K.strings(n, seed=71 + n % 11)
+    say(f"[gpu-build] strings n={n}, 128-bit hashes")
+    p = P.params_default(n, key_kind=P.KEY_BYTES, index_bits=32)
+    p.hash_bits = 128
+    b = P.build_bytes_device(*dev_strings(data, off), params=p, placement="device")
+    o = O.params_for(n)
+    o.hash_bits = 128
+    m = O.build_bytes(data, off, params=o)
+    same(b, m)
+    # and the query of the members, through the 128-bit query kernel, is the oracle's
+    g = P.Mphf.from_built(b)
+    got = g.query_bytes(*dev_strings(data, off))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32).astype(np.uint64), O.query_bytes(m, data, off))
+
+
 def test_device_string_build_errors_and_host_agreement():
     n = 3_000_000
     data, off = K.strings(n, seed=9)
@@ -215,11 +235,12 @@ def test_device_string_build_errors_and_host_agreement():
     with pytest.raises(P.PtrHashError) as e:
         P.build_bytes_device(*dev_strings(data2, off2), placement="device")
     assert e.value.code == P.E_DUPLICATE
-    # 128-bit string hashes are outside the device construction
+    # 128-bit string hashes: the device build equals the host build
     p = P.params_default(1000, key_kind=P.KEY_BYTES)
     p.hash_bits = 128
     d3, o3 = dev_strings(*K.strings(1000, seed=5))
-    with pytest.raises(P.PtrHashError) as e:
-        P.build_bytes_device(d3, o3, params=p, placement="device")
-    assert e.value.code == P.E_RANGE
-    assert P.build_bytes_device(d3, o3, params=p, placement="auto").placement == "host"
+    bd = P.build_bytes_device(d3, o3, params=p.copy(), placement="device")
+    bh = P.build_bytes_device(d3, o3, params=p.copy(), placement="host")
+    assert bd.placement == "device" and bh.placement == "host"
+    assert bd.params.seed == bh.params.seed
+    assert np.array_equal(bd.pilots, bh.pilots) and np.array_equal(bd.remap, bh.remap)
