@@ -30,6 +30,13 @@ constexpr int kRecent = 16;
 constexpr uint32_t kHeapCap = 1024;       // requeued buckets waiting at once
 constexpr uint32_t kMaxBucket = 2048;     // largest bucket searched (its slots fit the per-wave scratch)
 constexpr uint32_t kShuffleDistinct = 1;  // buckets up to this size set their bits without the tentative step
+constexpr int kMaxHelpers = 7;            // look-ahead wavefronts beside the leading one, at most
+constexpr int kMaxBlock = kWave * (1 + kMaxHelpers);
+constexpr uint32_t kRing = 42;            // look-ahead results held at once, entry e in ring[e % kRing];
+                                          // a multiple of every helper count allowed (1, 2, 3, 6, 7), so
+                                          // that each ring entry has a single writer
+constexpr uint32_t kNoPilot = 256;        // no pilot in [0, 256) has free, pairwise distinct slots
+constexpr uint64_t kTagBusy = ~0ull;      // a look-ahead result being written
 
 // Slot record written when a bucket is placed: owner bucket (local id), its
 // placement number, its size and its pilot.
@@ -176,6 +183,8 @@ struct PlaceArgs {
     uint32_t *status;           // per part
     uint64_t *evictions;        // per part
     uint32_t *cancel;           // set (by cancel_k) when this seed's result is no longer needed
+    const uint64_t *ostart;     // P*B: offset in OH of each order entry's hashes
+    uint32_t helpers;           // look-ahead wavefronts per workgroup (blockDim.x / 64 - 1)
 };
 
 // The cancel flag, read at agent scope so that a store from another stream's
@@ -199,9 +208,66 @@ __device__ __forceinline__ bool distinct_lanes(uint32_t q, uint32_t s) {
     return __ballot(dup) == 0;
 }
 
+// What a look-ahead wavefront found for one order entry (a bucket of at most
+// 64 keys): the bucket, the smallest pilot whose slots were free and
+// pairwise distinct in the bitvector it read (or kNoPilot), and that
+// pilot's slots. Written before the tag; once the leader has read its entry's
+// tag with the current generation the entry no longer changes (its one writer
+// moves on to later entries, and only the leader changes the generation).
+struct LookAhead {
+    uint64_t tag;            // (generation << 32) | entry; kTagBusy while written
+    uint32_t pilot;
+    uint32_t size, id;       // the bucket (size, local id) of the entry
+    uint32_t pad;
+    uint32_t slots[kWave];   // key j's slot in slots[j]
+};
+
+// The generation counts the leader's changes to the bitvector that clear
+// bits (evictions, undone tentative placements, a new part): it is odd
+// while one is under way. Between two changes bits are only added.
 struct LdsState {
     uint64_t heap[kHeapCap];  // max-heap of (size << 32) | ~id; its size lives in a register
+    LookAhead ring[kRing];
+    uint64_t gb0;             // first order entry of the part being searched
+    uint32_t gen;             // generation (written by the leader only)
+    uint32_t front;           // order entries of the part the leader has taken
+    uint32_t nb;              // order entries of the part
+    uint32_t done;            // the leader has finished
 };
+
+// LDS words shared by the wavefronts of the workgroup, each read or written
+// by one instruction. lds_fence orders this wavefront's LDS accesses before
+// it against those after it (it waits for LDS operations only, not for
+// global stores).
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t lds_ld(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uniform(uint64_t v) {
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
+// The leader's generation steps: open before it clears bits, close after.
+__device__ __forceinline__ void open_gen(LdsState &st, uint32_t &gen) {
+    gen |= 1u;
+    if (__lane_id() == 0) lds_st(&st.gen, gen);
+    lds_fence();
+}
+__device__ __forceinline__ void close_gen(LdsState &st, uint32_t &gen) {
+    lds_fence();
+    gen += 1u;
+    if (__lane_id() == 0) lds_st(&st.gen, gen);
+}
 
 // Heap operations run in every lane on the same values (LDS reads
 // broadcast); lane 0 writes. hn is the heap's size (wave-uniform).
@@ -281,14 +347,160 @@ struct Window {
     }
 };
 
-// One wavefront per workgroup; a persistent grid takes parts from a counter.
-// Mod: the single-part x mod S reduce instead of the power-of-two one.
+// Pilots p in [64 round, 64 round + 64) with p >= start, pilot p in lane
+// p % 64 of the result: none of the bucket's s keys (key j's hash in lane j
+// of h) lands on a taken slot with p. Four independent LDS reads per step.
 template <bool Mod>
-__global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
-    extern __shared__ uint32_t bits[];  // S bits of the current part
-    __shared__ LdsState st;
+__device__ __forceinline__ uint64_t free_pilots(const DevMphf &m, const uint32_t *bits, uint64_t h, uint32_t s,
+                                                int round, uint32_t start) {
+    const uint32_t pl = (uint32_t)(round * kWave + __lane_id());
+    const uint64_t hp = pilot_hash(m, pl);
+    bool free = pl >= start;
+    for (uint32_t j = 0; j < s; j += 4) {
+        bool t = is_taken(bits, local_slot<Mod>(m, bcast64(h, (int)j), hp));
+        if (j + 1 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h, (int)j + 1), hp));
+        if (j + 2 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h, (int)j + 2), hp));
+        if (j + 3 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h, (int)j + 3), hp));
+        free = free && !t;
+        if (__ballot(free) == 0) break;
+    }
+    return __ballot(free);
+}
+
+// A look-ahead wavefront (hid of nh). While the leader places buckets one by
+// one, it takes the part's order entries e = hid, hid + nh, ... that lie
+// less than kRing ahead of the leader and, for each bucket of at most 64
+// keys, records in ring[e % kRing] the smallest pilot whose slots are free
+// and pairwise distinct in the bitvector as it reads it, tagged with the
+// generation it read under. Within a generation bits are only added, so the
+// pilots below the recorded one stay blocked; the leader, finding its entry
+// tagged with the current generation, only re-checks the recorded slots. The
+// leader never waits for a look-ahead wavefront; these leave once it is done.
+// The order keys and hash offsets of its next 64 entries are loaded at once
+// (lane j: entry eb + j nh), and the hashes of the next bucket are loaded
+// while the current one is searched.
+template <bool Mod>
+__device__ __forceinline__ void look_ahead(const PlaceArgs &a, const uint32_t *bits, LdsState &st, uint32_t hid,
+                                           uint32_t nh) {
     const DevMphf &m = a.m;
     const int lane = __lane_id();
+    uint32_t hgen = 1u, e = hid;
+    uint64_t bgb = ~0ull, bk = 0, bo = 0;  // batch: part, order key and hash offset of entry eb + lane nh
+    uint32_t eb = 0;
+    uint64_t pgb = ~0ull, ph = 0;          // prefetched hashes of entry pe of part pgb
+    uint32_t pe = 0;
+    for (;;) {
+        if (uniform(lds_ld(&st.done))) break;
+        const uint32_t g1 = uniform(lds_ld(&st.gen));
+        lds_fence();
+        const uint64_t gb0 = uniform(lds_ld(&st.gb0));
+        const uint32_t nb = uniform(lds_ld(&st.nb)), front = uniform(lds_ld(&st.front));
+        lds_fence();
+        const uint32_t g2 = uniform(lds_ld(&st.gen));
+        if ((g1 & 1u) || g1 != g2) {
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        if (g1 != hgen) {  // a new generation: earlier results no longer count
+            hgen = g1;
+            e = hid;
+        }
+        if (e < front) e += (front - e + nh - 1) / nh * nh;
+        if (e >= nb || e >= front + kRing) {
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        if (bgb != gb0 || e < eb || e - eb >= (uint32_t)kWave * nh) {
+            const uint64_t ej = (uint64_t)e + (uint64_t)lane * nh;
+            bk = ej < nb ? a.okeys[gb0 + ej] : 0;
+            bo = ej < nb ? a.ostart[gb0 + ej] : 0;
+            bgb = gb0;
+            eb = e;
+        }
+        uint32_t s, id;
+        const int j = (int)((e - eb) / nh);
+        decode_key(bcast64(bk, j), a.max_size, a.size_bits, a.id_bits, s, id);
+        if (s == 0) {  // sizes only fall along the order: the rest are empty
+            e = nb;
+            continue;
+        }
+        if (s > (uint32_t)kWave) {
+            e += nh;
+            continue;
+        }
+        uint64_t h = ph;
+        if (pgb != gb0 || pe != e) {
+            const uint64_t c = bcast64(bo, j);
+            h = (uint32_t)lane < s ? a.OH[c + lane] : 0;
+        }
+        // h complete before the next load is issued, so that the search below
+        // does not wait for that load too (vmcnt cannot tell the two apart)
+        wait_vm();
+        // the next entry's hashes, in flight during this search
+        pgb = ~0ull;
+        if (j + 1 < kWave && e + nh < nb) {
+            uint32_t sn, idn;
+            decode_key(bcast64(bk, j + 1), a.max_size, a.size_bits, a.id_bits, sn, idn);
+            if (sn > 0 && sn <= (uint32_t)kWave) {
+                const uint64_t cn = bcast64(bo, j + 1);
+                ph = (uint32_t)lane < sn ? a.OH[cn + lane] : 0;
+                pgb = gb0;
+                pe = e + nh;
+            }
+        }
+        uint32_t pilot = kNoPilot, q = 0;
+        for (int round = 0; round < 4 && pilot == kNoPilot; ++round) {
+            uint64_t cand = free_pilots<Mod>(m, bits, h, s, round, 0);
+            while (cand) {
+                const int lbit = __builtin_ctzll(cand);
+                cand &= cand - 1;
+                const uint32_t pc = (uint32_t)(round * kWave + lbit);
+                const uint32_t qc = (uint32_t)lane < s ? local_slot<Mod>(m, h, pilot_hash(m, pc)) : 0u;
+                if (distinct_lanes(qc, s)) {
+                    pilot = pc;
+                    q = qc;
+                    break;
+                }
+            }
+        }
+        LookAhead &r = st.ring[e % kRing];
+        if (lane == 0) lds_st(&r.tag, kTagBusy);
+        lds_fence();
+        if ((uint32_t)lane < s) r.slots[lane] = q;
+        if (lane == 0) {
+            r.pilot = pilot;
+            r.size = s;
+            r.id = id;
+        }
+        lds_fence();
+        if (lane == 0) lds_st(&r.tag, ((uint64_t)g1 << 32) | e);
+        e += nh;
+    }
+}
+
+// One workgroup per part at a time, a persistent grid taking parts from a
+// counter: wavefront 0 places the buckets, the others look ahead for it.
+// Mod: the single-part x mod S reduce instead of the power-of-two one.
+template <bool Mod>
+__global__ void __launch_bounds__(kMaxBlock) place_k(PlaceArgs a) {
+    extern __shared__ uint32_t bits[];  // S bits of the current part
+    __shared__ LdsState st;
+    for (uint32_t i = threadIdx.x; i < kRing; i += blockDim.x) st.ring[i].tag = kTagBusy;
+    if (threadIdx.x == 0) {
+        st.gb0 = 0;
+        st.gen = 1u;
+        st.front = 0u;
+        st.nb = 0u;
+        st.done = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x >= (uint32_t)kWave) {
+        look_ahead<Mod>(a, bits, st, threadIdx.x / kWave - 1, a.helpers);
+        return;
+    }
+    const DevMphf &m = a.m;
+    const int lane = __lane_id();
+    uint32_t gen = 1u;  // the generation (odd: no part yet)
     const uint32_t S = m.reduce_kind == kReduceMod ? m.mod_slots : (1u << m.log2_slots);
     const uint32_t words = (S + 31) / 32;
     const uint32_t B = m.buckets;
@@ -302,11 +514,16 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
         p = (uint32_t)__builtin_amdgcn_readfirstlane((int)p);
         if (p >= m.parts) break;
 
+        const uint64_t gb0 = (uint64_t)p * B;
+        open_gen(st, gen);
+        if (lane == 0) {
+            lds_st(&st.gb0, gb0);
+            lds_st(&st.nb, B);
+            lds_st(&st.front, 0u);
+        }
         for (uint32_t w = lane; w < words; w += kWave) bits[w] = 0u;
         uint32_t hn = 0;  // requeued buckets in the heap
-        __builtin_amdgcn_wave_barrier();
-
-        const uint64_t gb0 = (uint64_t)p * B;
+        close_gen(st, gen);
         uint64_t k = gb0;                    // next entry of the search order
         const uint64_t kend = gb0 + B;
         uint64_t c = a.bst[gb0];             // its first hash in OH
@@ -324,9 +541,22 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             // next bucket: the larger of the order's head and the heap's top
             uint32_t s = 0, id = 0;
             bool from_order = false;
+            bool have = false;       // the look-ahead result for entry k, read under the current generation
+            uint32_t rp = 0, rq = 0; // its pilot and key `lane`'s slot
             if (k < kend) {
-                ow.need(k);
-                decode_key(ow.get(k), a.max_size, a.size_bits, a.id_bits, s, id);
+                const uint32_t e = (uint32_t)(k - gb0);
+                LookAhead &r = st.ring[e % kRing];
+                if (uniform(lds_ld(&r.tag)) == (((uint64_t)gen << 32) | e)) {
+                    lds_fence();
+                    s = uniform(r.size);
+                    id = uniform(r.id);
+                    rp = uniform(r.pilot);
+                    rq = (uint32_t)lane < s ? r.slots[lane] : 0u;
+                    have = true;
+                } else {
+                    ow.need(k);
+                    decode_key(ow.get(k), a.max_size, a.size_bits, a.id_bits, s, id);
+                }
                 from_order = s > 0;
             }
             if (hn > 0) {
@@ -342,15 +572,34 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             }
             const bool small = s <= kWave;
             const uint64_t *src;
-            uint64_t h0 = 0;  // key `lane` of a small bucket
+            uint64_t h0 = 0;     // key `lane` of a small bucket
+            int chosen = -1;
+            uint32_t myq = 0;    // key `lane`'s slot with the chosen pilot (small buckets)
+            uint32_t start = 0;  // the pilots below it are known to be blocked
             if (from_order) {
                 src = a.OH + c;
                 if (small) {
-                    hw.need(c);
-                    h0 = hw.lanes(c);
+                    if (have) {
+                        start = rp;
+                        if (rp < kNoPilot) {
+                            if (__ballot((uint32_t)lane < s && is_taken(bits, rq)) == 0) {
+                                // still free, and distinct (checked by the look-ahead)
+                                if ((uint32_t)lane < s) atomicOr(&bits[rq >> 5], 1u << (rq & 31));
+                                chosen = (int)rp;
+                                myq = rq;
+                            } else {
+                                start = rp + 1;
+                            }
+                        }
+                    }
+                    if (chosen < 0) {
+                        hw.need(c);
+                        h0 = hw.lanes(c);
+                    }
                 }
                 c += s;
                 ++k;
+                if (lane == 0) lds_st(&st.front, (uint32_t)(k - gb0));
             } else {
                 src = a.H + a.bst[gb0 + id];
                 if (small && (uint32_t)lane < s) h0 = src[lane];
@@ -358,24 +607,10 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             }
             if (!small && s > kMaxBucket) { status = kPlaceTooLarge; break; }
 
-            int chosen = -1;
             // 1) smallest pilot with free, distinct slots
             if (small) {
-                uint32_t myq = 0;
-                for (int round = 0; round < 4 && chosen < 0; ++round) {
-                    const uint32_t pl = (uint32_t)(round * kWave + lane);
-                    const uint64_t hp = pilot_hash(m, pl);
-                    bool free = true;
-                    // four independent LDS reads per step, then one test
-                    for (uint32_t j = 0; j < s; j += 4) {
-                        bool t = is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j), hp));
-                        if (j + 1 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 1), hp));
-                        if (j + 2 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 2), hp));
-                        if (j + 3 < s) t |= is_taken(bits, local_slot<Mod>(m, bcast64(h0, (int)j + 3), hp));
-                        free = free && !t;
-                        if (__ballot(free) == 0) break;
-                    }
-                    uint64_t cand = __ballot(free);
+                for (int round = (int)(start >> 6); round < 4 && chosen < 0; ++round) {
+                    uint64_t cand = free_pilots<Mod>(m, bits, h0, s, round, start);
                     while (cand) {
                         const int lbit = __builtin_ctzll(cand);
                         cand &= cand - 1;
@@ -398,8 +633,9 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                             if (old & (1u << (myq & 31))) dup = true; else mine = true;
                         }
                         if (__ballot(dup) == 0) { chosen = (int)pc; break; }
+                        open_gen(st, gen);  // bits are cleared
                         if (mine) atomicAnd(&bits[myq >> 5], ~(1u << (myq & 31)));
-                        __builtin_amdgcn_wave_barrier();
+                        close_gen(st, gen);
                     }
                 }
                 if (chosen >= 0) {
@@ -408,6 +644,33 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                     const SlotRec rec{id, (uint32_t)placed, s, (uint32_t)chosen};
                     if ((uint32_t)lane < s) recs[myq] = rec;
                     if (lane == 0) a.pilots[gb0 + id] = (uint8_t)chosen;
+                    // The entries that follow, as long as each is a look-ahead result
+                    // of the current generation whose slots are still free and no
+                    // requeued bucket waits: the same steps as above, in a loop of
+                    // their own. Only stores are in flight at its back edge, so the
+                    // compiler puts no wait for memory operations in it (at the
+                    // general loop's head it may, for loads of the slower paths, and
+                    // vmcnt counts the record stores too). Anything else goes back
+                    // to the general loop, which takes the same entry again.
+                    while (have && hn == 0 && k < kend && ((iter + 1) & 8191u) != 8191u && iter + 1 <= max_iter) {
+                        const uint32_t e = (uint32_t)(k - gb0);
+                        LookAhead &r = st.ring[e % kRing];
+                        if (uniform(lds_ld(&r.tag)) != (((uint64_t)gen << 32) | e)) break;
+                        lds_fence();
+                        const uint32_t s2 = uniform(r.size), id2 = uniform(r.id), p2 = uniform(r.pilot);
+                        if (p2 >= kNoPilot) break;
+                        const uint32_t q2 = (uint32_t)lane < s2 ? r.slots[lane] : 0u;
+                        if (__ballot((uint32_t)lane < s2 && is_taken(bits, q2))) break;
+                        if ((uint32_t)lane < s2) atomicOr(&bits[q2 >> 5], 1u << (q2 & 31));
+                        ++iter;
+                        ++placed;
+                        const SlotRec rec2{id2, (uint32_t)placed, s2, p2};
+                        if ((uint32_t)lane < s2) recs[q2] = rec2;
+                        if (lane == 0) a.pilots[gb0 + id2] = (uint8_t)p2;
+                        c += s2;
+                        ++k;
+                        if (lane == 0) lds_st(&st.front, (uint32_t)(k - gb0));
+                    }
                     continue;
                 }
             } else {
@@ -424,12 +687,13 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                         if (old & (1u << (qq & 31))) dup = true; else mine |= 1u << r;
                     }
                     if (__ballot(dup) == 0) { chosen = (int)pc; break; }
+                    open_gen(st, gen);  // bits are cleared
                     for (uint32_t t = lane, r = 0; t < s; t += kWave, ++r)
                         if (mine & (1u << r)) {
                             const uint32_t qq = local_slot<Mod>(m, src[t], hpc);
                             atomicAnd(&bits[qq >> 5], ~(1u << (qq & 31)));
                         }
-                    __builtin_amdgcn_wave_barrier();
+                    close_gen(st, gen);
                 }
             }
 
@@ -500,6 +764,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                 }
                 if (chosen < 0) { status = kPlaceFailed; break; }
                 // evict every owner the chosen slots hit, key by key
+                open_gen(st, gen);  // bits are cleared
                 const uint64_t hpc = pilot_hash(m, (uint32_t)chosen);
                 for (uint32_t j = 0; j < s; ++j) {
                     const uint64_t hj = small ? bcast64(h0, (int)j) : src[j];
@@ -527,7 +792,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
                     const uint32_t qq = local_slot<Mod>(m, small ? h0 : src[t], hpc);
                     atomicOr(&bits[qq >> 5], 1u << (qq & 31));
                 }
-                __builtin_amdgcn_wave_barrier();
+                close_gen(st, gen);
             }
 
             // slot records and pilot of the placed bucket
@@ -555,6 +820,7 @@ __global__ void __launch_bounds__(kWave) place_k(PlaceArgs a) {
             a.evictions[p] = ev;
         }
     }
+    if (lane == 0) lds_st(&st.done, 1u);
 }
 
 }  // namespace
@@ -724,6 +990,11 @@ class GpuSearch {
         m_.mod_slots = mod_ ? (uint32_t)S_ : 0;
         m_.mod_magic = mod_ ? ~0ull / S_ : 0;  // floor((2^64 - 1) / S) = floor(2^64 / S): S is not a power of two
         timing_ = std::getenv("PTRHASH_BUILD_TIMING") != nullptr;
+        // look-ahead wavefronts per part (0, 1, 2, 3, 6 or 7)
+        if (const char *la = std::getenv("PTRHASH_SEARCH_HELPERS")) {
+            const int h = std::atoi(la);
+            if (h == 0 || (h > 0 && h <= ptrhash::kMaxHelpers && ptrhash::kRing % h == 0)) helpers_ = (uint32_t)h;
+        }
         tick_ = std::chrono::steady_clock::now();
     }
 
@@ -734,6 +1005,9 @@ class GpuSearch {
         std::fprintf(stderr, "[build] %-10s %8.3f s\n", name, std::chrono::duration<double>(now - tick_).count());
         tick_ = now;
     }
+
+    // Threads per search workgroup: the leading wavefront and its helpers.
+    int block() const { return ptrhash::kWave * (1 + (int)helpers_); }
 
     // Limits of the device search and the buffers that do not depend on the
     // hash set.
@@ -754,10 +1028,10 @@ class GpuSearch {
         (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_);
         int per_cu = 0;
         if (mod_)
-            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<true>, kWave, lds_),
+            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<true>, block(), lds_),
                         "occupancy query");
         else
-            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<false>, kWave, lds_),
+            HIP_OR_FAIL(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, place_k<false>, block(), lds_),
                         "occupancy query");
         if (per_cu < 1) return set_error(PTRHASH_E_RANGE, "device placement does not fit one CU");
         grid_ = std::min<uint64_t>(P_, (uint64_t)cus * (uint64_t)per_cu);
@@ -935,10 +1209,12 @@ class GpuSearch {
         a.status = t.status;
         a.evictions = t.ev;
         a.cancel = t.cancel;
+        a.ostart = ostart_;
+        a.helpers = helpers_;
         if (mod_)
-            hipLaunchKernelGGL(place_k<true>, dim3((uint32_t)grid_), dim3(kWave), lds_, t.stream, a);
+            hipLaunchKernelGGL(place_k<true>, dim3((uint32_t)grid_), dim3(block()), lds_, t.stream, a);
         else
-            hipLaunchKernelGGL(place_k<false>, dim3((uint32_t)grid_), dim3(kWave), lds_, t.stream, a);
+            hipLaunchKernelGGL(place_k<false>, dim3((uint32_t)grid_), dim3(block()), lds_, t.stream, a);
         HIP_OR_FAIL(hipGetLastError(), "search launch");
         HIP_OR_FAIL(hipMemcpyAsync(t.status_h, t.status, P_ * sizeof(uint32_t), hipMemcpyDeviceToHost, t.stream),
                     "copy out");
@@ -1131,6 +1407,7 @@ class GpuSearch {
     uint64_t n_;
     hipStream_t stream_;
     bool mod_ = false, timing_ = false;
+    uint32_t helpers_ = 7;
     std::chrono::steady_clock::time_point tick_;
     uint64_t S_ = 0, P_ = 0, B_ = 0, total_ = 0, words_ = 0, grid_ = 0, taken_words_ = 0;
     size_t lds_ = 0, sort_temp_bytes_ = 0;

@@ -131,6 +131,28 @@ def test_side_by_side_seeds_equal_oracle(n, P_, log2, lam, kseed, stuck_ms, monk
     say(f"[gpu-build] attempts {b.info.attempts}")
 
 
+@pytest.mark.parametrize("helpers", ["0", "1", "2", "6", "7"])
+def test_device_search_helper_counts_equal_oracle(helpers, monkeypatch):
+    """Every count of look-ahead wavefronts (the default is 3; 0 runs the
+    leading wavefront alone) gives the oracle's pilots: at the default
+    parameters, with Compact's heavy evictions at S = 2^13, and with a
+    failing seed."""
+    monkeypatch.setenv("PTRHASH_SEARCH_HELPERS", helpers)
+    say(f"[gpu-build] look-ahead wavefronts {helpers}")
+    keys = K.u64_keys(600_000, seed=91)
+    b = P.build_u64_device(dev(keys), placement="device")
+    same(b, O.build_u64(keys))
+    for n, P_, log2, lam, kseed in [(30_000, 4, 13, 4.5, 20), (20_000, 1, 15, 4.0, 4)]:
+        keys = K.u64_keys(n, seed=kseed)
+        B = int(np.ceil(0.99 * (1 << log2) / lam))
+        m = O.build_u64(keys, params=O.params_explicit(n, P_, log2, B, seed=0))
+        p = lib_params(m)
+        p.seed = 0
+        b = P.build_u64_device(dev(keys), params=p, placement="device")
+        same(b, m)
+        assert b.info.attempts == m.stats.attempts
+
+
 def test_device_search_errors():
     keys = K.u64_keys(5000, seed=3)
     keys[4000] = keys[12]
