@@ -252,6 +252,10 @@ __device__ __forceinline__ void lds_st(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+// Keeps the compiler from moving memory accesses across it; no wait. A
+// wavefront's LDS operations are carried out in the order they are issued,
+// so a read issued after another also observes the LDS after it.
+__device__ __forceinline__ void compiler_fence() { __asm__ __volatile__("" ::: "memory"); }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ uint64_t uniform(uint64_t v) {
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
@@ -650,26 +654,53 @@ __global__ void __launch_bounds__(kMaxBlock) place_k(PlaceArgs a) {
                     // their own. Only stores are in flight at its back edge, so the
                     // compiler puts no wait for memory operations in it (at the
                     // general loop's head it may, for loads of the slower paths, and
-                    // vmcnt counts the record stores too). Anything else goes back
-                    // to the general loop, which takes the same entry again.
-                    while (have && hn == 0 && k < kend && ((iter + 1) & 8191u) != 8191u && iter + 1 <= max_iter) {
-                        const uint32_t e = (uint32_t)(k - gb0);
-                        LookAhead &r = st.ring[e % kRing];
-                        if (uniform(lds_ld(&r.tag)) != (((uint64_t)gen << 32) | e)) break;
-                        lds_fence();
-                        const uint32_t s2 = uniform(r.size), id2 = uniform(r.id), p2 = uniform(r.pilot);
-                        if (p2 >= kNoPilot) break;
-                        const uint32_t q2 = (uint32_t)lane < s2 ? r.slots[lane] : 0u;
-                        if (__ballot((uint32_t)lane < s2 && is_taken(bits, q2))) break;
-                        if ((uint32_t)lane < s2) atomicOr(&bits[q2 >> 5], 1u << (q2 & 31));
-                        ++iter;
-                        ++placed;
-                        const SlotRec rec2{id2, (uint32_t)placed, s2, p2};
-                        if ((uint32_t)lane < s2) recs[q2] = rec2;
-                        if (lane == 0) a.pilots[gb0 + id2] = (uint8_t)p2;
-                        c += s2;
-                        ++k;
-                        if (lane == 0) lds_st(&st.front, (uint32_t)(k - gb0));
+                    // vmcnt counts the record stores too). The next entry is read
+                    // while this one's slots are checked. Anything else goes back to
+                    // the general loop, which takes the same entry again.
+                    if (have && hn == 0 && k < kend) {
+                        uint32_t e = (uint32_t)(k - gb0), ri = e % kRing;
+                        uint64_t t2 = lds_ld(&st.ring[ri].tag);
+                        compiler_fence();
+                        uint32_t s2 = st.ring[ri].size, id2 = st.ring[ri].id, p2 = st.ring[ri].pilot;
+                        uint32_t q2 = st.ring[ri].slots[lane];
+                        while (((iter + 1) & 8191u) != 8191u && iter + 1 <= max_iter) {
+                            if (uniform(t2) != (((uint64_t)gen << 32) | e)) break;
+                            s2 = uniform(s2);
+                            id2 = uniform(id2);
+                            p2 = uniform(p2);
+                            if (p2 >= kNoPilot) break;
+                            // the bitvector words of this entry's slots (every lane reads:
+                            // no branch around the read, so the reads of the next entry,
+                            // its tag first, are issued before it is waited for)
+                            const uint32_t qa = (uint32_t)lane < s2 ? q2 : 0u;
+                            uint32_t w = bits[qa >> 5];
+                            const uint32_t r1 = ri + 1 == kRing ? 0u : ri + 1;
+                            compiler_fence();
+                            const uint64_t t3 = lds_ld(&st.ring[r1].tag);
+                            compiler_fence();
+                            const uint32_t s3 = st.ring[r1].size, id3 = st.ring[r1].id, p3 = st.ring[r1].pilot;
+                            const uint32_t q3 = st.ring[r1].slots[lane];
+                            compiler_fence();
+                            __asm__ __volatile__("" : "+v"(w));  // w is used only from here on
+                            if (__ballot((uint32_t)lane < s2 && ((w >> (qa & 31)) & 1u))) break;
+                            if ((uint32_t)lane < s2) atomicOr(&bits[q2 >> 5], 1u << (q2 & 31));
+                            ++iter;
+                            ++placed;
+                            const SlotRec rec2{id2, (uint32_t)placed, s2, p2};
+                            if ((uint32_t)lane < s2) recs[q2] = rec2;
+                            if (lane == 0) a.pilots[gb0 + id2] = (uint8_t)p2;
+                            c += s2;
+                            ++k;
+                            if (lane == 0) lds_st(&st.front, (uint32_t)(k - gb0));
+                            if (k >= kend) break;
+                            e += 1;
+                            ri = r1;
+                            t2 = t3;
+                            s2 = s3;
+                            id2 = id3;
+                            p2 = p3;
+                            q2 = q3;
+                        }
                     }
                     continue;
                 }
@@ -703,22 +734,41 @@ __global__ void __launch_bounds__(kMaxBlock) place_k(PlaceArgs a) {
                 // placements of this wavefront: wait for those stores.
                 __threadfence_block();
                 if (small) {
-                    uint64_t keyr[4];
-                    for (int round = 0; round < 4; ++round) {
-                        const uint32_t pl = (uint32_t)(round * kWave + lane);
-                        const uint64_t hp = pilot_hash(m, pl);
-                        uint64_t cost = 0;
-                        bool ok = true;
-                        for (uint32_t j = 0; j < s; ++j) {
-                            const uint32_t qq = local_slot<Mod>(m, bcast64(h0, (int)j), hp);
-                            if (ok && is_taken(bits, qq)) {
-                                const SlotRec rec = recs[qq];
-                                if ((uint64_t)rec.last + kRecent > placed) ok = false;
-                                cost += (uint64_t)rec.size * rec.size;
-                            }
+                    // Per lane, pilots lane, 64 + lane, 128 + lane and 192 + lane: the
+                    // sum over the keys on taken slots of the owner's size squared,
+                    // unless a slot belongs to a recently placed bucket. Four keys at a
+                    // time, the slot records of the four keys under all four pilots are
+                    // loaded unconditionally (a slot is below S; the record of a free
+                    // slot is not used), so that the sixteen loads are in flight together.
+                    uint64_t keyr[4], cost[4] = {0, 0, 0, 0};
+                    bool ok[4] = {true, true, true, true};
+                    for (uint32_t j = 0; j < s; j += 4) {
+                        uint32_t q[4][4];
+                        SlotRec rec[4][4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint32_t ji = j + (uint32_t)i < s ? j + (uint32_t)i : j;
+                            const uint64_t hj = bcast64(h0, (int)ji);
+#pragma unroll
+                            for (int round = 0; round < 4; ++round)
+                                q[round][i] = local_slot<Mod>(m, hj, pilot_hash(m, (uint32_t)(round * kWave + lane)));
                         }
-                        keyr[round] = ok ? ((cost << 8) | pl) : ~0ull;
+#pragma unroll
+                        for (int round = 0; round < 4; ++round)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) rec[round][i] = recs[q[round][i]];
+#pragma unroll
+                        for (int round = 0; round < 4; ++round)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (j + (uint32_t)i < s && ok[round] && is_taken(bits, q[round][i])) {
+                                    if ((uint64_t)rec[round][i].last + kRecent > placed) ok[round] = false;
+                                    cost[round] += (uint64_t)rec[round][i].size * rec[round][i].size;
+                                }
                     }
+#pragma unroll
+                    for (int round = 0; round < 4; ++round)
+                        keyr[round] = ok[round] ? ((cost[round] << 8) | (uint32_t)(round * kWave + lane)) : ~0ull;
                     // the least (cost, pilot) whose slots are distinct
                     for (int tries = 0; tries < 256; ++tries) {
                         uint64_t mn = keyr[0];
