@@ -194,11 +194,20 @@ __device__ __forceinline__ bool cancel_requested(uint32_t *flag) {
     return __builtin_amdgcn_readfirstlane((int)v) != 0;
 }
 
-// Pairwise distinctness of up to 64 slots, key j in lane j (j < s): lane a
-// compares with lane a+d mod 64 for d = 1..32, which covers every pair.
+// Pairwise distinctness of up to 64 slots, key j in lane j (j < s). Up to
+// eight keys, key j's slot is read into a scalar and compared by the lanes
+// after j (no LDS traffic); beyond, lane a compares with lane a+d mod 64
+// for d = 1..32, which covers every pair.
 __device__ __forceinline__ bool distinct_lanes(uint32_t q, uint32_t s) {
     const int lane = __lane_id();
     bool dup = false;
+    if (s <= 8) {
+        for (uint32_t j = 0; j + 1 < s; ++j) {
+            const uint32_t qj = (uint32_t)__builtin_amdgcn_readlane((int)q, (int)j);
+            dup |= (uint32_t)lane > j && (uint32_t)lane < s && q == qj;
+        }
+        return __ballot(dup) == 0;
+    }
     for (int d = 1; d <= kWave / 2; ++d) {
         if ((uint32_t)d >= s) break;
         const int src = (lane + d) & (kWave - 1);
@@ -395,12 +404,16 @@ __device__ __forceinline__ void look_ahead(const PlaceArgs &a, const uint32_t *b
     uint32_t pe = 0;
     for (;;) {
         if (uniform(lds_ld(&st.done))) break;
-        const uint32_t g1 = uniform(lds_ld(&st.gen));
-        lds_fence();
-        const uint64_t gb0 = uniform(lds_ld(&st.gb0));
-        const uint32_t nb = uniform(lds_ld(&st.nb)), front = uniform(lds_ld(&st.front));
-        lds_fence();
+        // generation, part and leader position, then the generation again,
+        // read in this order (LDS carries them out in issue order)
+        const uint32_t g1r = lds_ld(&st.gen);
+        compiler_fence();
+        const uint64_t gb0r = lds_ld(&st.gb0);
+        const uint32_t nbr = lds_ld(&st.nb), frontr = lds_ld(&st.front);
+        compiler_fence();
         const uint32_t g2 = uniform(lds_ld(&st.gen));
+        const uint32_t g1 = uniform(g1r), nb = uniform(nbr), front = uniform(frontr);
+        const uint64_t gb0 = uniform(gb0r);
         if ((g1 & 1u) || g1 != g2) {
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -467,16 +480,18 @@ __device__ __forceinline__ void look_ahead(const PlaceArgs &a, const uint32_t *b
                 }
             }
         }
+        // the entry marked busy, its contents, then its tag, written in this
+        // order (LDS carries them out in issue order)
         LookAhead &r = st.ring[e % kRing];
         if (lane == 0) lds_st(&r.tag, kTagBusy);
-        lds_fence();
+        compiler_fence();
         if ((uint32_t)lane < s) r.slots[lane] = q;
         if (lane == 0) {
             r.pilot = pilot;
             r.size = s;
             r.id = id;
         }
-        lds_fence();
+        compiler_fence();
         if (lane == 0) lds_st(&r.tag, ((uint64_t)g1 << 32) | e);
         e += nh;
     }
