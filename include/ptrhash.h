@@ -360,10 +360,13 @@ PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrha
 /* As ptrhash_build_u64 with the keys in device memory and the whole pilot
  * search on the device too (Section 3.2 "Construction"): the hashes are
  * radix-sorted, bucket boundaries and a per-part (size descending, bucket
- * id) order are built on the device, and one wavefront per part runs the
- * hash-evict search with the part's taken-slot bitvector in LDS. The result
- * is the same as ptrhash_build_u64 on the same keys, byte for byte; only the
- * remap table is assembled on the host from the taken-slot bitvector.
+ * id) order are built on the device, and one workgroup per part runs the
+ * hash-evict search: one wavefront places the buckets with the part's
+ * taken-slot bitvector in LDS while look-ahead wavefronts find the smallest
+ * free pilot of the buckets it will take next (PTRHASH_SEARCH_HELPERS = 0, 1,
+ * 2, 3, 6 or 7 sets their number; 7 by default). The result is the same as
+ * ptrhash_build_u64 on the same keys, byte for byte, whatever that number;
+ * only the remap table is assembled on the host from the taken-slot bitvector.
  * Limits: the S bits of a part must fit one workgroup's LDS (S <= 2^20 on
  * gfx950), S a multiple of 32 when P > 1, buckets of at most 2048 keys;
  * outside them the call returns E_RANGE and ptrhash_build_u64_device

@@ -25,6 +25,7 @@ through the server, every index equal to the oracle's query of the
 request's own MPHF.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -166,7 +167,9 @@ def test_u64_beyond_2_32_keys():
         pytest.skip(f"needs ~200 GiB of free device memory, {free / 2**30:.0f} GiB free")
     say(f"[fullsize] u64 n={n}: device keys + device construction")
     keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=DEV), K.KEY_SEED)
+    t0 = time.time()
     built = P.build_u64_device(keys, index_bits=64, placement="device")
+    say(f"[fullsize] construction {time.time() - t0:.1f} s, {built.info.evictions} evictions")
     check_params(built.params, n)
     assert built.params.num_parts * (1 << built.params.log2_slots) > 2**32
     torch.cuda.empty_cache()
