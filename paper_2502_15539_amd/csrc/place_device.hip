@@ -1,10 +1,12 @@
 // Pilot search on the device (Section 3.2 "Construction"; the hash-evict
 // search of Section 3.2 "Hash-evict", the 10*S eviction limit of Section 4).
 //
-// Parts are independent, so each part is searched by one wavefront that owns
-// the part's taken-slot bitvector in LDS (S bits; 128 KiB at S = 2^20). The
-// rules are exactly those of the host builder, so the device reaches the same
-// pilots: buckets in order of (size descending, bucket id ascending); the
+// Parts are independent, so each part is searched by one workgroup that owns
+// the part's taken-slot bitvector in LDS (S bits; 128 KiB at S = 2^20): one
+// wavefront places the buckets, the others look ahead for it (look_ahead
+// below). The rules are exactly those of the host builder, so the device
+// reaches the same pilots: buckets in order of (size descending, bucket id
+// ascending); the
 // smallest pilot in [0, 256) whose slots are free and pairwise distinct;
 // otherwise, among pilots with distinct slots that touch none of the 16 most
 // recently placed buckets, the one with the least sum over colliding keys of
