@@ -612,18 +612,6 @@ int check_build_params(uint64_t n, const ptrhash_params *params, uint32_t key_ki
     return check_geometry(params);
 }
 
-int remap_from_taken(const ptrhash_params *params, const std::vector<uint64_t> &taken, void *remap) {
-    const bool mod = params->reduce_kind == PTRHASH_REDUCE_MOD;
-    Geometry g{params->n, params->num_parts, mod ? params->slots : 1ull << params->log2_slots,
-               params->buckets_per_part, params->seed, params->log2_slots, params->gamma, mod};
-    if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
-    try {
-        return write_remap(g, params, taken, remap);
-    } catch (const std::bad_alloc &) {
-        return set_error(PTRHASH_E_NOMEM, "host allocation failed building the remap");
-    }
-}
-
 int build_from_sorted(std::vector<uint64_t> &&sorted, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                       void *remap, int threads, ptrhash_build_info *info) {
     KeySource src;

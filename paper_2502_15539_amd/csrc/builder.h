@@ -16,7 +16,4 @@ int build_from_sorted(std::vector<uint64_t> &&sorted, uint64_t n, ptrhash_params
 // kind match params, and the geometry is one the library can hold.
 int check_build_params(uint64_t n, const ptrhash_params *params, uint32_t key_kind);
 
-// The remap (Section 3.4) from the taken-slot bitvector of all P*S slots
-// (bit q of word q/64), written to remap in params->remap_kind's encoding.
-int remap_from_taken(const ptrhash_params *params, const std::vector<uint64_t> &taken, void *remap);
 }  // namespace ptrhash

@@ -1014,6 +1014,94 @@ __global__ void cancel_k(uint32_t *flag) {
     if (threadIdx.x == 0) atomicExch(flag, 1u);
 }
 
+// ---------------------------------------------------------------------------
+// The remap table (Section 3.4) from the taken-slot bitvector (slot q is bit
+// q & 63 of u64 word q >> 6): F[q - n] for the slots q in [n, P*S) is, where
+// q is taken, the next free slot below n, both taken in increasing order;
+// elsewhere it repeats its predecessor (0 before the first). Then F is
+// encoded into CacheLineEF lines (or written as u32). The same table as the
+// host builder's, byte for byte.
+
+// Bits of the word whose first slot is base that lie below slot lim.
+__device__ __forceinline__ uint64_t bits_below(uint64_t base, uint64_t lim) {
+    if (lim <= base) return 0;
+    return lim - base >= 64 ? ~0ull : (1ull << (lim - base)) - 1;
+}
+
+// Per word: free slots below n, taken slots in [n, total).
+__global__ void remap_counts_k(const uint64_t *__restrict__ taken, uint64_t words, uint64_t n, uint64_t total,
+                               uint64_t *__restrict__ cfree, uint64_t *__restrict__ ctaken) {
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = w * 64, v = taken[w], below = bits_below(base, n);
+        cfree[w] = (uint64_t)__popcll(~v & below);
+        ctaken[w] = (uint64_t)__popcll(v & bits_below(base, total) & ~below);
+    }
+}
+
+// The free slots below n in increasing order (ofree: exclusive prefix sums of cfree).
+__global__ void remap_free_list_k(const uint64_t *__restrict__ taken, uint64_t words, uint64_t n,
+                                  const uint64_t *__restrict__ ofree, uint64_t *__restrict__ fl) {
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = w * 64;
+        uint64_t f = ~taken[w] & bits_below(base, n), o = ofree[w];
+        while (f) {
+            fl[o++] = base + (uint64_t)__builtin_ctzll(f);
+            f &= f - 1;
+        }
+    }
+}
+
+// F[t], t < len: the free slot matched with the last taken slot in
+// [n, n + t], or 0 if there is none (otaken: exclusive prefix sums of ctaken).
+__global__ void remap_values_k(const uint64_t *__restrict__ taken, uint64_t n, uint64_t len,
+                               const uint64_t *__restrict__ otaken, const uint64_t *__restrict__ fl,
+                               uint64_t *__restrict__ F) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = n + t, w = q >> 6, b = q & 63, base = w * 64;
+        const uint64_t upto = b == 63 ? ~0ull : (2ull << b) - 1;
+        const uint64_t r = otaken[w] + (uint64_t)__popcll(taken[w] & ~bits_below(base, n) & upto);
+        F[t] = r ? fl[r - 1] : 0;
+    }
+}
+
+// One CacheLineEF line per thread: the offset F[first] >> 8 (32 bits), a
+// 128-bit map with bit i + (F[first + i] >> 8) - offset set for each of
+// the line's values, and their low bytes (eq. clef). err: 1 = an offset
+// beyond 32 bits, 2 = a line whose values span too far.
+__global__ void remap_clef_k(const uint64_t *__restrict__ F, uint64_t len, uint32_t *__restrict__ out,
+                             uint32_t *__restrict__ err) {
+    const uint64_t lines = (len + 43) / 44;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < lines; c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t first = c * 44, cnt = len - first < 44 ? len - first : 44;
+        const uint64_t off = F[first] >> 8;
+        uint32_t e = off > 0xffffffffull ? 1u : 0u;
+        uint64_t m0 = 0, m1 = 0;
+        uint32_t low[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (uint64_t i = 0; i < cnt; ++i) {
+            const uint64_t v = F[first + i], b = i + (v >> 8) - off;
+            if (b > 127) {
+                e |= 2u;
+                continue;
+            }
+            if (b < 64) m0 |= 1ull << b; else m1 |= 1ull << (b - 64);
+            low[i >> 2] |= (uint32_t)(v & 255) << (8 * (i & 3));
+        }
+        uint32_t *line = out + c * 16;
+        line[0] = (uint32_t)off;
+        line[1] = (uint32_t)m0;
+        line[2] = (uint32_t)(m0 >> 32);
+        line[3] = (uint32_t)m1;
+        line[4] = (uint32_t)(m1 >> 32);
+        for (int i = 0; i < 11; ++i) line[5 + i] = low[i];
+        if (e) atomicOr(err, e);
+    }
+}
+
+__global__ void remap_u32_k(const uint64_t *__restrict__ F, uint64_t len, uint32_t *__restrict__ out) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (uint64_t)gridDim.x * blockDim.x)
+        out[t] = (uint32_t)F[t];
+}
+
 // The buffers of one seed's search. Slot 0 runs on the caller's stream; the
 // others, used when seeds run side by side, on streams of their own.
 struct Attempt {
@@ -1432,6 +1520,70 @@ class GpuSearch {
         return set_error(PTRHASH_E_BUILD, "construction failed for %d seeds", kMaxSeeds);
     }
 
+    // The remap table from a finished search's taken-slot bitvector, built on
+    // the device and copied to remap (host memory; none for REMAP_NONE).
+    int device_remap(const ptrhash_params &p, Attempt &t, void *remap) {
+        using namespace ptrhash;
+        const uint64_t total = P_ * S_, len = total - n_, words = (total + 63) / 64;
+        const uint64_t *taken = reinterpret_cast<const uint64_t *>(t.taken);
+        hipStream_t s = t.stream;
+        if (!rm_cfree_) {
+            HIP_OR_FAIL(buf_.get(&rm_cfree_, words), "remap counts");
+            HIP_OR_FAIL(buf_.get(&rm_ctaken_, words), "remap counts");
+            HIP_OR_FAIL(buf_.get(&rm_ofree_, words), "remap offsets");
+            HIP_OR_FAIL(buf_.get(&rm_otaken_, words), "remap offsets");
+            HIP_OR_FAIL(buf_.get(&rm_err_, 1), "remap flags");
+        }
+        const dim3 grid(4096), block(256);
+        hipLaunchKernelGGL(remap_counts_k, grid, block, 0, s, taken, words, n_, total, rm_cfree_, rm_ctaken_);
+        HIP_OR_FAIL(hipGetLastError(), "remap counts launch");
+        for (int i = 0; i < 2; ++i) {
+            const uint64_t *in = i ? rm_ctaken_ : rm_cfree_;
+            uint64_t *out = i ? rm_otaken_ : rm_ofree_;
+            size_t temp = 0;
+            HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(nullptr, temp, in, out, (int64_t)words, s), "scan sizing");
+            if (temp > sort_temp_bytes_) {
+                HIP_OR_FAIL(buf_.get(&sort_temp_, temp), "scan scratch");
+                sort_temp_bytes_ = temp;
+            }
+            HIP_OR_FAIL(hipcub::DeviceScan::ExclusiveSum(sort_temp_, temp, in, out, (int64_t)words, s), "scan");
+        }
+        // the numbers of free slots below n and of taken slots at or above n must agree
+        uint64_t last[4] = {0, 0, 0, 0};
+        HIP_OR_FAIL(hipMemcpyAsync(&last[0], rm_ofree_ + words - 1, 8, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(&last[1], rm_cfree_ + words - 1, 8, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(&last[2], rm_otaken_ + words - 1, 8, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(&last[3], rm_ctaken_ + words - 1, 8, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(s), "copy out");
+        const uint64_t nfree = last[0] + last[1], ntaken = last[2] + last[3];
+        if (ntaken > nfree) return set_error(PTRHASH_E_BUILD, "remap: fewer free slots than overflow");
+        if (ntaken < nfree) return set_error(PTRHASH_E_BUILD, "remap: unmatched free slot");
+        const uint64_t rbytes = ptrhash_remap_bytes(&p);
+        if (!rbytes || !len) return PTRHASH_OK;
+        uint64_t *fl = nullptr, *F = nullptr;
+        uint32_t *enc = nullptr;
+        HIP_OR_FAIL(buf_.get(&fl, nfree), "remap free list");
+        HIP_OR_FAIL(buf_.get(&F, len), "remap values");
+        HIP_OR_FAIL(buf_.get(&enc, (rbytes + 3) / 4), "remap table");
+        HIP_OR_FAIL(hipMemsetAsync(rm_err_, 0, sizeof(uint32_t), s), "memset");
+        hipLaunchKernelGGL(remap_free_list_k, grid, block, 0, s, taken, words, n_, rm_ofree_, fl);
+        HIP_OR_FAIL(hipGetLastError(), "remap free list launch");
+        hipLaunchKernelGGL(remap_values_k, grid, block, 0, s, taken, n_, len, rm_otaken_, fl, F);
+        HIP_OR_FAIL(hipGetLastError(), "remap values launch");
+        if (p.remap_kind == PTRHASH_REMAP_CLEF)
+            hipLaunchKernelGGL(remap_clef_k, grid, block, 0, s, F, len, enc, rm_err_);
+        else
+            hipLaunchKernelGGL(remap_u32_k, grid, block, 0, s, F, len, enc);
+        HIP_OR_FAIL(hipGetLastError(), "remap encode launch");
+        uint32_t err = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(&err, rm_err_, sizeof err, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_OR_FAIL(hipMemcpyAsync(remap, enc, rbytes, hipMemcpyDeviceToHost, s), "remap to host");
+        HIP_OR_FAIL(hipStreamSynchronize(s), "copy out");
+        if (err & 1u) return set_error(PTRHASH_E_REMAP_RANGE, "remap value beyond 40 bits");
+        if (err & 2u) return set_error(PTRHASH_E_REMAP_RANGE, "a CacheLineEF line spans too far");
+        return PTRHASH_OK;
+    }
+
     // After a successful search: pilots and remap to the host, statistics.
     int finish(ptrhash_params *params, uint64_t seed, uint8_t *pilots, void *remap, ptrhash_build_info *info,
                uint64_t attempts) {
@@ -1447,20 +1599,8 @@ class GpuSearch {
             local.evictions += t.ev_h[p];
             local.max_part_evictions = std::max(local.max_part_evictions, t.ev_h[p]);
         }
-        std::vector<uint64_t> taken;
-        try {
-            taken.resize(taken_words_ / 2);
-        } catch (const std::bad_alloc &) {
-            return set_error(PTRHASH_E_NOMEM, "host taken-slot bitvector");
-        }
         HIP_OR_FAIL(hipMemcpyAsync(pilots, t.pil, total_, hipMemcpyDeviceToHost, t.stream), "pilots to host");
-        HIP_OR_FAIL(hipMemcpyAsync(taken.data(), t.taken, taken_words_ * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                   t.stream),
-                    "taken bits to host");
-        HIP_OR_FAIL(hipStreamSynchronize(t.stream), "copy out");
-        ptrhash_params out = *params;
-        out.seed = seed;
-        if (int rc = remap_from_taken(&out, taken, remap)) return rc;
+        if (int rc = device_remap(*params, t, remap)) return rc;
         phase("remap");
         params->seed = seed;
         if (info) *info = local;
@@ -1490,6 +1630,8 @@ class GpuSearch {
     uint64_t *OH_ = nullptr;
     uint64_t max_size_ = 0;
     uint32_t size_bits_ = 0, id_bits_ = 0;
+    uint64_t *rm_cfree_ = nullptr, *rm_ctaken_ = nullptr, *rm_ofree_ = nullptr, *rm_otaken_ = nullptr;
+    uint32_t *rm_err_ = nullptr;
 };
 
 int build_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots, void *remap,
