@@ -366,12 +366,13 @@ PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrha
  * free pilot of the buckets it will take next (PTRHASH_SEARCH_HELPERS = 0, 1,
  * 2, 3, 6 or 7 sets their number; 7 by default). The result is the same as
  * ptrhash_build_u64 on the same keys, byte for byte, whatever that number;
- * only the remap table is assembled on the host from the taken-slot bitvector.
+ * the remap table is built on the device too, from the taken-slot bitvector.
  * Limits: the S bits of a part must fit one workgroup's LDS (S <= 2^20 on
  * gfx950), S a multiple of 32 when P > 1, buckets of at most 2048 keys;
  * outside them the call returns E_RANGE and ptrhash_build_u64_device
- * (host search) applies. Device memory: about 16*n + 33*P*B + P*S/8 bytes
- * plus 16*S bytes per compute unit, for the duration of the call. A seed
+ * (host search) applies. Device memory: about 16*n + 33*P*B + 5*P*S/8 +
+ * 20*(P*S - n) bytes plus 16*S bytes per compute unit, for the duration of
+ * the call. A seed
  * whose search runs three times longer than a normal one would (a part
  * caught in an eviction cycle) has the next three seeds searched beside it
  * on streams of the library's own, each with another P*B + P*S/8 + 16*S per
@@ -395,7 +396,8 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
  * both halves collide. E_RANGE when more than 64 pairs of keys share a hash
  * (the host construction examines them all) or, with 128-bit hashes, three
  * keys share a high half. Device memory: about 32*n (48*n with 128-bit
- * hashes) + 33*P*B + P*S/8 bytes plus 16*S bytes per compute unit. Seeds
+ * hashes) + 33*P*B + 5*P*S/8 + 20*(P*S - n) bytes plus 16*S bytes per
+ * compute unit. Seeds
  * are searched one after the other. */
 PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
                                         ptrhash_params *params, uint8_t *pilots, void *remap,
