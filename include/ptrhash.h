@@ -372,16 +372,15 @@ PTRHASH_API int ptrhash_build_u64_device(const uint64_t *keys, uint64_t n, ptrha
  * outside them the call returns E_RANGE and ptrhash_build_u64_device
  * (host search) applies. Device memory: about 16*n + 33*P*B + 5*P*S/8 +
  * 20*(P*S - n) bytes plus 16*S bytes per compute unit, for the duration of
- * the call. A seed
- * whose search runs three times longer than a normal one would (a part
- * caught in an eviction cycle) has the next three seeds searched beside it
- * on streams of the library's own, each with another P*B + P*S/8 + 16*S per
- * compute unit of device memory when that much is free; seeds are still
- * taken in order, so the result does not change (PTRHASH_SPECULATE_MS sets
- * the threshold in ms). stream orders the device work and is synchronised
- * before return. Errors: E_INVAL,
- * E_DUPLICATE, E_BUILD (a part with more than S keys, or 16 failed seeds),
- * E_RANGE, E_NOMEM, E_HIP. */
+ * the call. A seed whose search runs three times longer than a normal one
+ * would (a part caught in an eviction cycle) has the next three seeds
+ * searched beside it on streams of the library's own, each with another
+ * P*B + P*S/8 + 16*S per compute unit of device memory when that much is
+ * free; seeds are still taken in order, so the result does not change
+ * (PTRHASH_SPECULATE_MS sets the threshold in ms). stream orders the device
+ * work and is synchronised before return. Errors: E_INVAL, E_DUPLICATE,
+ * E_BUILD (a part with more than S keys, or 16 failed seeds), E_RANGE,
+ * E_NOMEM, E_HIP. */
 PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_params *params, uint8_t *pilots,
                                       void *remap, ptrhash_build_info *info, hipStream_t stream);
 
