@@ -774,11 +774,18 @@ __global__ void __launch_bounds__(kMaxBlock) place_k(PlaceArgs a) {
                         for (int round = 0; round < 4; ++round)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) rec[round][i] = recs[q[round][i]];
+                        // the sixteen taken bits, read together (bit 4 round + i)
+                        uint32_t tk = 0;
+#pragma unroll
+                        for (int round = 0; round < 4; ++round)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) tk |= (uint32_t)is_taken(bits, q[round][i]) << (4 * round + i);
+                        __asm__ __volatile__("" : "+v"(tk));  // every read issued before any is used
 #pragma unroll
                         for (int round = 0; round < 4; ++round)
 #pragma unroll
                             for (int i = 0; i < 4; ++i)
-                                if (j + (uint32_t)i < s && ok[round] && is_taken(bits, q[round][i])) {
+                                if (j + (uint32_t)i < s && ok[round] && ((tk >> (4 * round + i)) & 1u)) {
                                     if ((uint64_t)rec[round][i].last + kRecent > placed) ok[round] = false;
                                     cost[round] += (uint64_t)rec[round][i].size * rec[round][i].size;
                                 }
