@@ -184,15 +184,16 @@ struct PlaceArgs {
     uint32_t *next_part;        // work counter, zeroed
     uint32_t *status;           // per part
     uint64_t *evictions;        // per part
-    uint32_t *cancel;           // set (by cancel_k) when this seed's result is no longer needed
+    uint32_t *cancel;           // set by the host when this seed's result is no longer needed
     const uint64_t *ostart;     // P*B: offset in OH of each order entry's hashes
     uint32_t helpers;           // look-ahead wavefronts per workgroup (blockDim.x / 64 - 1)
 };
 
-// The cancel flag, read at agent scope so that a store from another stream's
-// kernel is seen; wave-uniform.
+// The cancel flag, in coherent pinned host memory that the host sets while
+// the search runs; read at system scope so that the host's store is seen.
+// Wave-uniform.
 __device__ __forceinline__ bool cancel_requested(uint32_t *flag) {
-    const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return __builtin_amdgcn_readfirstlane((int)v) != 0;
 }
 
@@ -499,6 +500,46 @@ __device__ __forceinline__ void look_ahead(const PlaceArgs &a, const uint32_t *b
     }
 }
 
+// The eviction cost step for keys j .. j+N-1 of a small bucket (key j's hash
+// in lane j of h0) under the pilots lane, 64 + lane, 128 + lane and
+// 192 + lane: for each taken slot, the owner's size squared is added to
+// cost[round], and ok[round] is cleared if the owner is among the recently
+// placed buckets. The 4 N slot records are loaded unconditionally (a slot is
+// below S; the record of a free slot is not used) and the 4 N taken bits read
+// together, so that the loads of the group are in flight at once.
+template <bool Mod, int N>
+__device__ __forceinline__ void cost_group(const DevMphf &m, const uint32_t *bits, const SlotRec *recs, uint64_t h0,
+                                           uint32_t j, uint64_t placed, uint64_t (&cost)[4], bool (&ok)[4]) {
+    const int lane = __lane_id();
+    uint32_t q[4][N];
+    SlotRec rec[4][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint64_t hj = bcast64(h0, (int)j + i);
+#pragma unroll
+        for (int round = 0; round < 4; ++round)
+            q[round][i] = local_slot<Mod>(m, hj, pilot_hash(m, (uint32_t)(round * kWave + lane)));
+    }
+#pragma unroll
+    for (int round = 0; round < 4; ++round)
+#pragma unroll
+        for (int i = 0; i < N; ++i) rec[round][i] = recs[q[round][i]];
+    uint32_t tk = 0;  // bit N round + i: the slot of key j + i under the round's pilot is taken
+#pragma unroll
+    for (int round = 0; round < 4; ++round)
+#pragma unroll
+        for (int i = 0; i < N; ++i) tk |= (uint32_t)is_taken(bits, q[round][i]) << (N * round + i);
+    __asm__ __volatile__("" : "+v"(tk));  // every read issued before any is used
+#pragma unroll
+    for (int round = 0; round < 4; ++round)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (ok[round] && ((tk >> (N * round + i)) & 1u)) {
+                if ((uint64_t)rec[round][i].last + kRecent > placed) ok[round] = false;
+                cost[round] += (uint64_t)rec[round][i].size * rec[round][i].size;
+            }
+}
+
 // One workgroup per part at a time, a persistent grid taking parts from a
 // counter: wavefront 0 places the buckets, the others look ahead for it.
 // Mod: the single-part x mod S reduce instead of the power-of-two one.
@@ -753,42 +794,20 @@ __global__ void __launch_bounds__(kMaxBlock) place_k(PlaceArgs a) {
                 if (small) {
                     // Per lane, pilots lane, 64 + lane, 128 + lane and 192 + lane: the
                     // sum over the keys on taken slots of the owner's size squared,
-                    // unless a slot belongs to a recently placed bucket. Four keys at a
-                    // time, the slot records of the four keys under all four pilots are
-                    // loaded unconditionally (a slot is below S; the record of a free
-                    // slot is not used), so that the sixteen loads are in flight together.
+                    // unless a slot belongs to a recently placed bucket; up to four keys
+                    // at a time (cost_group).
                     uint64_t keyr[4], cost[4] = {0, 0, 0, 0};
                     bool ok[4] = {true, true, true, true};
                     for (uint32_t j = 0; j < s; j += 4) {
-                        uint32_t q[4][4];
-                        SlotRec rec[4][4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const uint32_t ji = j + (uint32_t)i < s ? j + (uint32_t)i : j;
-                            const uint64_t hj = bcast64(h0, (int)ji);
-#pragma unroll
-                            for (int round = 0; round < 4; ++round)
-                                q[round][i] = local_slot<Mod>(m, hj, pilot_hash(m, (uint32_t)(round * kWave + lane)));
-                        }
-#pragma unroll
-                        for (int round = 0; round < 4; ++round)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) rec[round][i] = recs[q[round][i]];
-                        // the sixteen taken bits, read together (bit 4 round + i)
-                        uint32_t tk = 0;
-#pragma unroll
-                        for (int round = 0; round < 4; ++round)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) tk |= (uint32_t)is_taken(bits, q[round][i]) << (4 * round + i);
-                        __asm__ __volatile__("" : "+v"(tk));  // every read issued before any is used
-#pragma unroll
-                        for (int round = 0; round < 4; ++round)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                if (j + (uint32_t)i < s && ok[round] && ((tk >> (4 * round + i)) & 1u)) {
-                                    if ((uint64_t)rec[round][i].last + kRecent > placed) ok[round] = false;
-                                    cost[round] += (uint64_t)rec[round][i].size * rec[round][i].size;
-                                }
+                        const uint32_t left = s - j;
+                        if (left >= 4)
+                            cost_group<Mod, 4>(m, bits, recs, h0, j, placed, cost, ok);
+                        else if (left == 3)
+                            cost_group<Mod, 3>(m, bits, recs, h0, j, placed, cost, ok);
+                        else if (left == 2)
+                            cost_group<Mod, 2>(m, bits, recs, h0, j, placed, cost, ok);
+                        else
+                            cost_group<Mod, 1>(m, bits, recs, h0, j, placed, cost, ok);
                     }
 #pragma unroll
                     for (int round = 0; round < 4; ++round)
@@ -1015,12 +1034,6 @@ __global__ void equal_pairs_k(const uint64_t *__restrict__ H, const uint64_t *__
         }
 }
 
-// Stop the search of a seed whose result is no longer needed (one lane, a
-// vector atomic at agent scope; runs on its own stream beside the search).
-__global__ void cancel_k(uint32_t *flag) {
-    if (threadIdx.x == 0) atomicExch(flag, 1u);
-}
-
 // ---------------------------------------------------------------------------
 // The remap table (Section 3.4) from the taken-slot bitvector (slot q is bit
 // q & 63 of u64 word q >> 6): F[q - n] for the slots q in [n, P*S) is, where
@@ -1116,7 +1129,8 @@ struct Attempt {
     bool own_stream = false;
     hipEvent_t done = nullptr;
     uint8_t *pil = nullptr;
-    uint32_t *taken = nullptr, *big = nullptr, *next = nullptr, *status = nullptr, *cancel = nullptr;
+    uint32_t *taken = nullptr, *big = nullptr, *next = nullptr, *status = nullptr;
+    uint32_t *cancel = nullptr;    // coherent pinned host memory: set by the host, read by the search
     ptrhash::SlotRec *recs = nullptr;
     uint64_t *ev = nullptr;
     uint32_t *status_h = nullptr;  // pinned host copies, filled by the search's stream
@@ -1215,8 +1229,8 @@ class GpuSearch {
             if (t.own_stream && t.stream) (void)hipStreamDestroy(t.stream);
             if (t.status_h) (void)hipHostFree(t.status_h);
             if (t.ev_h) (void)hipHostFree(t.ev_h);
+            if (t.cancel) (void)hipHostFree(t.cancel);
         }
-        if (ctrl_) (void)hipStreamDestroy(ctrl_);
         if (prepared_) (void)hipEventDestroy(prepared_);
     }
 
@@ -1235,11 +1249,12 @@ class GpuSearch {
         HIP_OR_FAIL(buf_.get(&t.recs, grid_ * S_), "slot records");
         HIP_OR_FAIL(buf_.get(&t.big, grid_ * (uint64_t)kMaxBucket), "bucket scratch");
         HIP_OR_FAIL(buf_.get(&t.next, 1), "work counter");
-        HIP_OR_FAIL(buf_.get(&t.cancel, 1), "cancel flag");
         HIP_OR_FAIL(buf_.get(&t.status, P_), "part status");
         HIP_OR_FAIL(buf_.get(&t.ev, P_), "part evictions");
         HIP_OR_FAIL(hipHostMalloc(&t.status_h, P_ * sizeof(uint32_t), hipHostMallocDefault), "pinned status");
         HIP_OR_FAIL(hipHostMalloc(&t.ev_h, P_ * sizeof(uint64_t), hipHostMallocDefault), "pinned evictions");
+        HIP_OR_FAIL(hipHostMalloc(&t.cancel, sizeof(uint32_t), hipHostMallocCoherent), "cancel flag");
+        __atomic_store_n(t.cancel, 0u, __ATOMIC_SEQ_CST);
         HIP_OR_FAIL(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "event");
         if (own_stream) {
             HIP_OR_FAIL(hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking), "stream");
@@ -1350,7 +1365,7 @@ class GpuSearch {
         HIP_OR_FAIL(hipMemsetAsync(t.pil, 0, total_, t.stream), "memset");
         HIP_OR_FAIL(hipMemsetAsync(t.taken, 0, taken_words_ * sizeof(uint32_t), t.stream), "memset");
         HIP_OR_FAIL(hipMemsetAsync(t.next, 0, sizeof(uint32_t), t.stream), "memset");
-        HIP_OR_FAIL(hipMemsetAsync(t.cancel, 0, sizeof(uint32_t), t.stream), "memset");
+        __atomic_store_n(t.cancel, 0u, __ATOMIC_SEQ_CST);  // the slot's previous search has finished
         PlaceArgs a{};
         a.m = m_;
         a.m.seed = seed;
@@ -1441,17 +1456,15 @@ class GpuSearch {
             avail -= attempt_bytes();
             ++slots;
         }
-        if (!ctrl_ && slots > 1 && hipStreamCreateWithFlags(&ctrl_, hipStreamNonBlocking) != hipSuccess) return 1;
         return slots;
     }
 
-    // Cancel every running search but `keep` and wait for them to stop.
+    // Cancel every running search but `keep` and wait for them to stop. The
+    // flag is a host store into coherent memory, so it does not queue behind
+    // any device work.
     void cancel_others(const Attempt *keep) {
         for (Attempt &t : att_)
-            if (t.busy && &t != keep && ctrl_) {
-                hipLaunchKernelGGL(cancel_k, dim3(1), dim3(64), 0, ctrl_, t.cancel);
-                (void)hipGetLastError();
-            }
+            if (t.busy && &t != keep) __atomic_store_n(t.cancel, 1u, __ATOMIC_SEQ_CST);
         for (Attempt &t : att_)
             if (t.busy && &t != keep) {
                 (void)hipEventSynchronize(t.done);
@@ -1631,7 +1644,6 @@ class GpuSearch {
     uint32_t *flags_ = nullptr;
     uint8_t *sort_temp_ = nullptr;
     std::vector<Attempt> att_;
-    hipStream_t ctrl_ = nullptr;     // cancel kernels
     hipEvent_t prepared_ = nullptr;  // the search order is ready
     const uint64_t *H_ = nullptr, *okeys_ = nullptr;
     uint64_t *OH_ = nullptr;
