@@ -58,12 +58,35 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, int lane) {  // lane is 
     return ((uint64_t)hi << 32) | lo;
 }
 
+// v from another lane of its row of 16 by a DPP move (ctrl: the lane
+// pattern); a lane whose source is inactive keeps its own v.
+template <int Ctrl>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)v, (int)(uint32_t)v, Ctrl, 0xf, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(v >> 32), (int)(uint32_t)(v >> 32), Ctrl, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The least v of the wavefront (every lane active), in every lane: within
+// each row of 16 lanes by DPP moves (lanes of a quad swapped in pairs, then
+// in halves; then each half-row and each row mirrored), then the four rows'
+// minima read into scalars. No LDS traffic.
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint64_t o = shfl64(v, __lane_id() ^ d);
-        v = o < v ? o : v;
+    uint64_t o = dpp64<0xB1>(v);  // quad_perm 1,0,3,2
+    v = o < v ? o : v;
+    o = dpp64<0x4E>(v);           // quad_perm 2,3,0,1
+    v = o < v ? o : v;
+    o = dpp64<0x141>(v);          // row_half_mirror
+    v = o < v ? o : v;
+    o = dpp64<0x140>(v);          // row_mirror
+    v = o < v ? o : v;
+    uint64_t m = bcast64(v, 0);
+    for (int r = 16; r < kWave; r += 16) {
+        const uint64_t x = bcast64(v, r);
+        m = x < m ? x : m;
     }
-    return v;
+    return m;
 }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
