@@ -1,4 +1,4 @@
-"""Serving workload driver: many resident MPHFs, Poisson arrivals of query
+"""Serving workload: many resident MPHFs, Poisson arrivals of query
 batches of mixed sizes, continuous batching through ``ptrhash.Server``.
 
 Workload: 64 MPHFs with n log-uniform in [1e4, 1e7] over uniform u64 keys
