@@ -107,6 +107,29 @@ uint64_t orc_slot2(const orc_params *p, uint64_t h_part, uint64_t h_slot, uint32
  * On success *p may carry a new seed (reseeded after failed attempts). */
 int orc_build_u64(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
                   uint8_t *pilots, uint64_t *F, orc_build_stats *st);
+
+/* One record per bucket placement, in the order the search makes them, so
+ * that tests can check each decision of the hash-evict search against the
+ * rule of Section 3.2 on instances built by hand. Recording only observes:
+ * the construction is the same with or without it. */
+typedef struct {
+    uint64_t part;
+    uint32_t bucket;          /* local bucket id within the part */
+    uint32_t pilot;           /* pilot chosen */
+    uint32_t evicted;         /* buckets this placement evicted */
+    uint32_t attempt;         /* seed attempt, from 0 */
+    uint64_t part_evictions;  /* evictions in this part so far, this one included */
+} orc_trace_rec;
+
+typedef struct {
+    orc_trace_rec *rec;
+    uint64_t cap;    /* records rec can hold */
+    uint64_t len;    /* records written (at most cap) */
+    uint64_t total;  /* placements made */
+} orc_trace;
+
+int orc_build_u64_traced(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
+                         uint8_t *pilots, uint64_t *F, orc_build_stats *st, orc_trace *trace);
 int orc_build_bytes(orc_params *p, const uint8_t *data, const uint64_t *offsets,
                     const orc_build_cfg *cfg, uint8_t *pilots, uint64_t *F,
                     orc_build_stats *st);

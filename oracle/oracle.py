@@ -66,6 +66,21 @@ class BuildStats(C.Structure):
     ]
 
 
+class TraceRec(C.Structure):
+    _fields_ = [
+        ("part", C.c_uint64),
+        ("bucket", C.c_uint32),
+        ("pilot", C.c_uint32),
+        ("evicted", C.c_uint32),
+        ("attempt", C.c_uint32),
+        ("part_evictions", C.c_uint64),
+    ]
+
+
+class Trace(C.Structure):
+    _fields_ = [("rec", C.POINTER(TraceRec)), ("cap", C.c_uint64), ("len", C.c_uint64), ("total", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -98,6 +113,8 @@ def lib():
             "orc_reduce": (u64, [u64, u64]),
             "orc_slot": (u64, [P(Params), u64, C.c_uint32]),
             "orc_build_u64": (C.c_int, [P(Params), C.c_void_p, P(BuildCfg), C.c_void_p, C.c_void_p, P(BuildStats)]),
+            "orc_build_u64_traced": (C.c_int, [P(Params), C.c_void_p, P(BuildCfg), C.c_void_p, C.c_void_p,
+                                               P(BuildStats), P(Trace)]),
             "orc_build_bytes": (C.c_int, [P(Params), C.c_void_p, C.c_void_p, P(BuildCfg), C.c_void_p, C.c_void_p,
                                           P(BuildStats)]),
             "orc_clef_bytes": (u64, [u64]),
@@ -198,6 +215,25 @@ def build_u64(keys: np.ndarray, params: Params | None = None, eviction_factor=10
     rc = lib().orc_build_u64(C.byref(p), _ptr(keys), C.byref(_cfg(eviction_factor, max_attempts)), _ptr(pilots),
                              _ptr(F), C.byref(st))
     return _finish(p, pilots, F, st, rc)
+
+
+def build_u64_traced(keys: np.ndarray, params: Params, eviction_factor=10, max_attempts=16, cap=1 << 20):
+    """Build like ``build_u64`` and also return the search's placement
+    records. Never raises on a failed build: returns ``(rc, pilots, records,
+    stats)`` with ``records`` a list of dicts (part, bucket, pilot, evicted,
+    attempt, part_evictions) in placement order."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    p = Params.from_buffer_copy(params)
+    assert p.n == len(keys)
+    pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
+    F = np.zeros(max(1, p.remap_len), dtype=np.uint64)
+    st = BuildStats()
+    buf = (TraceRec * cap)()
+    tr = Trace(C.cast(buf, C.POINTER(TraceRec)), cap, 0, 0)
+    rc = lib().orc_build_u64_traced(C.byref(p), _ptr(keys), C.byref(_cfg(eviction_factor, max_attempts)),
+                                    _ptr(pilots), _ptr(F), C.byref(st), C.byref(tr))
+    recs = [{f: getattr(buf[i], f) for f, _ in TraceRec._fields_} for i in range(tr.len)]
+    return rc, pilots, recs, st
 
 
 def build_bytes(data: np.ndarray, offsets: np.ndarray, params: Params | None = None, eviction_factor=10,

@@ -429,6 +429,8 @@ typedef struct {
     uint32_t *heap_buf;
     uint64_t *slots;        /* scratch, one entry per key of the largest bucket */
     uint64_t *victim_slots; /* same size */
+    orc_trace *trace;       /* optional record of every placement */
+    uint32_t attempt;
 } part_ctx;
 
 /* Local slot of every key of local bucket b under pilot p; returns the
@@ -493,6 +495,7 @@ static int place_part(part_ctx *c, uint64_t part, uint64_t max_evictions, orc_bu
     while (heap.len) {
         uint32_t b = heap_pop(&heap);
         int chosen = -1;
+        uint64_t evicted = 0;
         for (uint32_t pl = 0; pl < 256 && chosen < 0; pl++) {
             uint64_t s = bucket_slots(c, part, b, pl, slots);
             if (!distinct(slots, s)) continue;
@@ -518,6 +521,7 @@ static int place_part(part_ctx *c, uint64_t part, uint64_t max_evictions, orc_bu
             }
             if (chosen < 0) return ORC_EPART_FAIL;
             uint64_t s = bucket_slots(c, part, b, (uint32_t)chosen, slots);
+            uint64_t before = evictions;
             uint64_t *victim_slots = c->victim_slots;
             for (uint64_t j = 0; j < s; j++) {
                 int64_t o = c->owner[slots[j]];
@@ -527,11 +531,25 @@ static int place_part(part_ctx *c, uint64_t part, uint64_t max_evictions, orc_bu
                 heap_push(&heap, (uint32_t)o);
                 evictions++;
             }
+            evicted = evictions - before;
         }
         uint64_t s = bucket_slots(c, part, b, (uint32_t)chosen, slots);
         for (uint64_t j = 0; j < s; j++) c->owner[slots[j]] = b;
         c->pilots[part * B + b] = (uint8_t)chosen;
         st->placements++;
+        if (c->trace) {
+            orc_trace *tr = c->trace;
+            if (tr->len < tr->cap) {
+                orc_trace_rec *r = &tr->rec[tr->len++];
+                r->part = part;
+                r->bucket = b;
+                r->pilot = (uint32_t)chosen;
+                r->evicted = (uint32_t)evicted;
+                r->attempt = c->attempt;
+                r->part_evictions = evictions;
+            }
+            tr->total++;
+        }
         recent[recent_pos] = b;
         recent_pos = (recent_pos + 1) % RECENT;
         if (evictions > max_evictions) return ORC_EPART_FAIL;
@@ -555,7 +573,7 @@ typedef int (*same_key_fn)(const void *ctx, uint64_t a, uint64_t b);
  */
 static int build_attempt(const orc_params *p, const uint64_t *h, const uint64_t *hs, same_key_fn same,
                          const void *sctx, uint8_t *pilots, uint64_t *F, orc_build_stats *st,
-                         uint64_t max_evictions)
+                         uint64_t max_evictions, orc_trace *trace, uint32_t attempt)
 {
     uint64_t n = p->n, P = p->num_parts, S = p->slots_per_part, B = p->buckets_per_part;
     uint64_t nb = P * B;
@@ -609,6 +627,8 @@ static int build_attempt(const orc_params *p, const uint64_t *h, const uint64_t 
     c.heap_buf = heap_buf;
     c.slots = slots;
     c.victim_slots = victim_slots;
+    c.trace = trace;
+    c.attempt = attempt;
     for (uint64_t part = 0; part < P; part++) {
         rc = place_part(&c, part, max_evictions, st);
         if (rc) goto out;
@@ -678,6 +698,12 @@ static void default_cfg(const orc_build_cfg *cfg, uint64_t *factor, uint64_t *at
 int orc_build_u64(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
                   uint8_t *pilots, uint64_t *F, orc_build_stats *st)
 {
+    return orc_build_u64_traced(p, keys, cfg, pilots, F, st, NULL);
+}
+
+int orc_build_u64_traced(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
+                         uint8_t *pilots, uint64_t *F, orc_build_stats *st, orc_trace *trace)
+{
     if (!p || !keys || !pilots || (p->remap_len && !F)) return ORC_EINVAL;
     orc_build_stats local;
     if (!st) st = &local;
@@ -692,7 +718,8 @@ int orc_build_u64(orc_params *p, const uint64_t *keys, const orc_build_cfg *cfg,
         orc_build_stats s1;
         memset(&s1, 0, sizeof s1);
         st->attempts = a + 1;
-        rc = build_attempt(p, h, h, same_u64, keys, pilots, F, &s1, factor * p->slots_per_part);
+        rc = build_attempt(p, h, h, same_u64, keys, pilots, F, &s1, factor * p->slots_per_part, trace,
+                           (uint32_t)a);
         st->placements += s1.placements;
         st->max_bucket_size = s1.max_bucket_size;
         if (rc != ORC_EPART_FAIL) {
@@ -736,7 +763,8 @@ int orc_build_bytes(orc_params *p, const uint8_t *data, const uint64_t *offsets,
         orc_build_stats s1;
         memset(&s1, 0, sizeof s1);
         st->attempts = a + 1;
-        rc = build_attempt(p, h, hs, same_bytes, &bc, pilots, F, &s1, factor * p->slots_per_part);
+        rc = build_attempt(p, h, hs, same_bytes, &bc, pilots, F, &s1, factor * p->slots_per_part, NULL,
+                           (uint32_t)a);
         st->placements += s1.placements;
         st->max_bucket_size = s1.max_bucket_size;
         if (rc != ORC_EPART_FAIL && rc != ORC_EPART_OVERFLOW) {
