@@ -93,6 +93,26 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """Host threads the CPU baselines use and what the host offers: the
+    threads this process may run on (its affinity mask), capped at the CPU
+    share of one GPU on a shared box (OMP_NUM_THREADS, else 16), plus nproc
+    and the CPU model."""
+    affinity = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": max(1, min(affinity, share)), "affinity_cpus": affinity, "nproc": os.cpu_count(),
+            "omp_num_threads": share, "cpu_model": model}
+
+
 def time_launches(torch, fn, steps, warmup):
     """Average duration of fn() (one kernel launch) on torch's current stream."""
     for _ in range(warmup):
@@ -168,9 +188,11 @@ def profiled_traffic(workload, ms, n):
     if t.get("kernel_source_sha256") != profsum.kernel_source_hash():
         return None, {"stale_profile": os.path.relpath(path, ROOT)}
     b = t["traffic_bytes_per_launch"]
-    return b, {"traffic_GBps": b / (ms / 1e3) / 1e9, "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-               "traffic_bytes_per_key": b / n,
-               "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "source": os.path.relpath(path, ROOT)}
+    info = {"level": t.get("level", ""), "traffic_GBps": b / (ms / 1e3) / 1e9,
+            "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic_bytes_per_key": b / n,
+            "read_bytes": t.get("read_bytes"), "write_bytes": t.get("write_bytes"),
+            "dram_read_requests": t.get("dram_read_requests"), "source": os.path.relpath(path, ROOT)}
+    return b, info
 
 
 def profiled_valu(workload, ms, kernel):
@@ -267,7 +289,8 @@ def oracle_baseline(args, p, built, q, out, bits, n, P=None):
     c0 = time.perf_counter()
     O.query_u64(m, one, O.REMAP_CLEF)
     single = (time.perf_counter() - c0) / len(one)
-    cores = min(16, os.cpu_count() or 1)
+    host = host_cpu()
+    cores = host["threads"]
     chunks = np.array_split(qs, cores)
     c0 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
@@ -279,7 +302,7 @@ def oracle_baseline(args, p, built, q, out, bits, n, P=None):
     cpu = {"value": ns / cdt, "unit": "queries/s", "cores": cores, "kind": "oracle", "ns_per_key": cdt / ns * 1e9,
            "sample": f"first {ns} queries of the same shuffled stream on the same MPHF, the C oracle's plain query "
                      f"loop on {cores} threads (one slice each)",
-           "single_thread_ns_per_key": single * 1e9, "single_thread_sample": len(one),
+           "single_thread_ns_per_key": single * 1e9, "single_thread_sample": len(one), "host": host,
            "matches_gpu": bool(np.array_equal(res, go))}
     log(f"[bench] cpu oracle: {cores} threads {cdt / ns * 1e9:.2f} ns/key, one thread {single * 1e9:.1f} ns/key, "
         f"matches_gpu={cpu['matches_gpu']}")
@@ -308,7 +331,8 @@ def oracle_baseline_bytes(args, p, built, qd, qo, out, n):
     c0 = time.perf_counter()
     run(0, one)
     single = (time.perf_counter() - c0) / one
-    cores = min(16, os.cpu_count() or 1)
+    host = host_cpu()
+    cores = host["threads"]
     bounds = np.linspace(0, ns, cores + 1).astype(np.int64)
     c0 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
@@ -319,7 +343,7 @@ def oracle_baseline_bytes(args, p, built, qd, qo, out, n):
     cpu = {"value": ns / cdt, "unit": "queries/s", "cores": cores, "kind": "oracle", "ns_per_key": cdt / ns * 1e9,
            "sample": f"first {ns} strings of the same shuffled stream on the same MPHF, the C oracle's plain query "
                      f"loop on {cores} threads (one slice each)",
-           "single_thread_ns_per_key": single * 1e9, "single_thread_sample": one,
+           "single_thread_ns_per_key": single * 1e9, "single_thread_sample": one, "host": host,
            "matches_gpu": bool(np.array_equal(res, go))}
     log(f"[bench] cpu oracle: {cores} threads {cdt / ns * 1e9:.2f} ns/key, one thread {single * 1e9:.1f} ns/key, "
         f"matches_gpu={cpu['matches_gpu']}")
@@ -375,10 +399,16 @@ def run_u64(args, torch, K, P):
               for c in gcands}
     gbest = min(gsweep, key=gsweep.get)
     gather_ms = gsweep[gbest]
+    # like-for-like: the same pilot table read at each key's own bucket (the
+    # cubic bucket function's skew included), no slot hash, no remap
+    bsweep = {c: time_launches(torch, lambda: P.bench_gather_buckets(mphf, q, gout, c[0], c[1], c[2]), 3, 1)
+              for c in gcands}
+    bbest = min(bsweep, key=bsweep.get)
+    bucket_ms = bsweep[bbest]
     copy_ms = min(time_launches(torch, lambda: P.bench_copy(q, gout, k, 256), 3, 1) for k in (1, 4, 8))
     del gout, table
-    log(f"[bench] query {ms:.3f} ms  gather-roofline {gather_ms:.3f} ms {gbest}  copy {copy_ms:.3f} ms  "
-        f"bijective={bij} remap_frac={rfrac:.5f}")
+    log(f"[bench] query {ms:.3f} ms  gather-roofline {gather_ms:.3f} ms {gbest}  own-bucket gather {bucket_ms:.3f} "
+        f"ms {bbest}  copy {copy_ms:.3f} ms  bijective={bij} remap_frac={rfrac:.5f}")
 
     cpu = None
     if args.cpu_sample and p.remap_kind == P.REMAP_CLEF and p.gamma == P.GAMMA_CUBIC:
@@ -394,7 +424,14 @@ def run_u64(args, torch, K, P):
                  pct_gather_roofline=100.0 * gather_ms / ms,
                  gather_roofline={"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
                                   "block": gbest[1], "blocks_per_cu": gbest[2],
-                                  "table_bytes": p.num_parts * p.buckets_per_part},
+                                  "table_bytes": p.num_parts * p.buckets_per_part,
+                                  "index": "uniform hi(key * T) over a table of the pilot array's size"},
+                 pct_bucket_gather_roofline=100.0 * bucket_ms / ms,
+                 bucket_gather_roofline={"ms": bucket_ms, "ns_per_key": bucket_ms * 1e6 / n,
+                                         "keys_per_lane": bbest[0], "block": bbest[1], "blocks_per_cu": bbest[2],
+                                         "index": "each key's own global bucket in the MPHF's pilot array (same "
+                                                  "hash, part and bucket function as the query; no slot hash, "
+                                                  "no remap)"},
                  stream_copy_ms=copy_ms,
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
                  cpu_baseline=cpu,
@@ -492,18 +529,38 @@ def run_bytes(args, torch, K, P):
     qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_bytes_into(qd, qo, out), args, n,
-                                          bytes_keys=True)
+    mphf.query_bytes_into(qd, qo, out)  # checks once that the strings end 64 bytes before the buffer does
+    best, sweep, ms, wall = tune_and_time(torch, P, mphf, lambda: mphf.query_bytes_into(qd, qo, out, check_end=False),
+                                          args, n, bytes_keys=True)
     bij = bijective(torch, out, n)
     rfrac = remap_fraction(torch, P, p, built.pilots, data=qd, offsets=qo)
     per_key = total_bytes / n + 8 + 4 + 1 + rfrac * 64
-    log(f"[bench] query {ms:.3f} ms bijective={bij}")
+    # string-stream roofline: the same offsets, string words and u32 index
+    # streams and one pilot byte per key, with the hash reduced to a xor fold
+    from paper_2502_15539_amd import autotune
+
+    gout = torch.empty(n, dtype=torch.int32, device="cuda")
+    gcands = [(k, b, o) for k in (1, 2, 4) for b in autotune.DEFAULT_BLOCKS for o in autotune.DEFAULT_OCCUPANCY]
+    if args.gather != "auto":
+        g = tuple(int(x) for x in args.gather.split(","))
+        gcands = [g if len(g) == 3 else g + (0,)]
+    gsweep = {c: time_launches(torch, lambda: P.bench_gather_bytes(mphf, qd, qo, gout, c[0], c[1], c[2]), 3, 1)
+              for c in gcands}
+    gbest = min(gsweep, key=gsweep.get)
+    gather_ms = gsweep[gbest]
+    del gout
+    log(f"[bench] query {ms:.3f} ms  string-stream gather roofline {gather_ms:.3f} ms {gbest}  bijective={bij}")
     cpu = oracle_baseline_bytes(args, p, built, qd, qo, out, n) if args.cpu_sample else None
     rec = record(args, n, ms, wall, desc,
                  {"kernel": kernel_name(P, best), "index_bits": bits, "num_parts": p.num_parts,
                   "bits_per_key": round(built.bits_per_key, 4), "mean_key_bytes": total_bytes / n},
                  "u64", per_key,
                  plain_kernel_ms=sweep.get((P.KERNEL_PLAIN, 1, 256, 0)),
+                 pct_gather_roofline=100.0 * gather_ms / ms,
+                 gather_roofline={"ms": gather_ms, "ns_per_key": gather_ms * 1e6 / n, "keys_per_lane": gbest[0],
+                                  "block": gbest[1], "blocks_per_cu": gbest[2],
+                                  "index": "string-stream gather: offsets, the string words and the u32 index "
+                                           "streamed, one pilot byte at the bucket of a xor fold of the words"},
                  cpu_baseline=cpu,
                  parity={"bijective_members": bij, "remap_fraction": rfrac}, build_s=t2 - t1,
                  build_search=built.placement,

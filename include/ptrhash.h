@@ -146,31 +146,41 @@ PTRHASH_API int ptrhash_get_params(const ptrhash_handle *h, ptrhash_params *out)
  * elements of index_bits. Members map bijectively onto [0, n); any other key
  * gets a deterministic value in [0, n) (minimal remaps) or [0, P*S) (no
  * remap). Asynchronous on stream; keys/out must stay valid until it
- * completes and must not overlap. n_q == 0 launches nothing. Errors:
- * E_STATE (not loaded, or a byte-key MPHF), E_INVAL (null), E_HIP.
+ * completes. n_q == 0 launches nothing. Any n_q is taken: batches beyond
+ * 2^31 work-items are split into several launches on the same stream.
+ * Errors: E_STATE (not loaded, or a byte-key MPHF), E_INVAL (null, or the
+ * byte ranges of keys and out overlap), E_HIP.
  */
 PTRHASH_API int ptrhash_query(ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, void *out,
                               hipStream_t stream);
 
 /*
- * As ptrhash_query for byte-string keys: key i is data[offsets[i] ..
- * offsets[i+1]). data: device, 8-byte aligned, with at least 64 readable
- * bytes after offsets[n_q]; offsets: device, n_q+1 u64, non-decreasing.
- * Errors: E_STATE (not loaded, or a u64-key MPHF), E_INVAL.
+ * As ptrhash_query for byte-string keys (Section 3.1, "Hash functions"):
+ * key i is data[offsets[i] .. offsets[i+1]). data: device, 8-byte aligned,
+ * data_len bytes, which must include at least 64 readable bytes after
+ * offsets[n_q]; offsets: device, n_q+1 u64, non-decreasing. The offsets
+ * live on the device, so they are checked by the kernel: a key whose end
+ * precedes its start, or which ends later than data_len - 16, is not read
+ * and gets an index of all ones (no valid index, unless n = 2^index_bits).
+ * Errors: E_STATE (not loaded, or a u64-key MPHF), E_INVAL (null, data not
+ * aligned, data_len < 64, or out overlapping data or offsets), E_HIP.
  */
-PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, const uint64_t *offsets,
-                                    uint64_t n_q, void *out, hipStream_t stream);
+PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, uint64_t data_len,
+                                    const uint64_t *offsets, uint64_t n_q, void *out, hipStream_t stream);
 
 /* ---- Many MPHFs in one launch (row A8) ---- */
 
 /* One query batch against one loaded MPHF. For a u64-key handle set keys;
- * for a byte-key handle set data (8-byte aligned, 64 bytes of readable
- * padding) and offsets (n_q+1 entries). out holds n_q indices of the
- * handle's index_bits. All pointers are device pointers. */
+ * for a byte-key handle set data (8-byte aligned, data_len bytes with 64
+ * bytes of readable padding after the last string, as in
+ * ptrhash_query_bytes) and offsets (n_q+1 entries). out holds n_q indices of
+ * the handle's index_bits. All pointers are device pointers. No batch's out
+ * may overlap its own or another batch's out, keys, data or offsets. */
 typedef struct ptrhash_query_desc {
     ptrhash_handle *handle;
     const uint64_t *keys;
     const uint8_t *data;
+    uint64_t data_len;
     const uint64_t *offsets;
     uint64_t n_q;
     void *out;
@@ -225,7 +235,9 @@ PTRHASH_API int ptrhash_multi_max(void);
 
 /* ---- Serving: continuous batching over resident MPHFs (row A8) ---- */
 
-/* streams: launch slots in flight at once (1..16); max_batches: requests per
+/* streams: launch slots in flight at once (1..16; a process gets
+ * GPU_MAX_HW_QUEUES hardware queues, 4 by default, and streams beyond that
+ * share them, so more than 4 slots add queueing, not concurrency); max_batches: requests per
  * launch (1..ptrhash_multi_max()); slot_keys: keys one launch can hold (its
  * device arena; also the largest request); max_queued_keys: admission limit
  * of keys waiting for a slot (submit returns E_RANGE beyond it);
@@ -252,6 +264,10 @@ typedef struct ptrhash_server_metrics {
     double p50_us, p99_us, max_us;  /* submit -> indices delivered, over the most recent
                                        2^20 requests completed since the last reset */
     double wait_p50_us, wait_p99_us; /* submit -> launch enqueued (queueing + copy-in), same window */
+    uint64_t slots_busy_max; /* most launch slots busy at once since the last reset (launched, not retired) */
+    uint64_t overlap_max;    /* most launches running at once on the device, from each launch's start and
+                                done events (timing events on its stream), over the most recent 2^16 */
+    double overlap_mean;     /* mean number of launches running over the time at least one runs, same window */
 } ptrhash_server_metrics;
 
 /* One request of a replayed arrival schedule (host keys and output). */
@@ -431,6 +447,25 @@ PTRHASH_API int ptrhash_bench_gather_pair(uint64_t n, const uint8_t *table, uint
                                           uint32_t lanes, uint32_t xor_dist, hipStream_t stream);
 PTRHASH_API int ptrhash_bench_copy(const uint64_t *keys, uint64_t n_q, uint64_t *out, int keys_per_lane,
                                    int block, hipStream_t stream);
+/* like-for-like gather of a loaded u64-key MPHF: out[i] = keys[i] xor
+ * pilots[bucket(keys[i])], the query's own hash, part and global bucket
+ * (eq. partbucket) without the slot hash and the remap, so the gathers hit
+ * the caches as the query's do (keys/out: device, n_q u64). */
+PTRHASH_API int ptrhash_bench_gather_buckets(ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, uint64_t *out,
+                                             int keys_per_lane, int block, int blocks_per_cu, hipStream_t stream);
+/* string-stream gather of a loaded MPHF: for each key of (data, data_len,
+ * offsets) as in ptrhash_query_bytes, read its offsets and the aligned words
+ * of its bytes, fold them by xor, mix once, read the pilot of the bucket
+ * that value maps to, and stream a u32 out (the memory pattern of a byte-key
+ * query without the string hash's arithmetic). */
+PTRHASH_API int ptrhash_bench_gather_bytes(ptrhash_handle *h, const uint8_t *data, uint64_t data_len,
+                                           const uint64_t *offsets, uint64_t n_q, uint32_t *out, int keys_per_lane,
+                                           int block, int blocks_per_cu, hipStream_t stream);
+/* un-permute probe: out[(i * A) mod 2^log2_n] = in[i] for every i < 2^log2_n
+ * (A odd, so every slot of out is written once): one streamed read and one
+ * random 8-byte write per element. in/out: device, 2^log2_n u64 each,
+ * log2_n in [8, 34]. */
+PTRHASH_API int ptrhash_bench_scatter(const uint64_t *in, uint32_t log2_n, uint64_t *out, hipStream_t stream);
 
 /* ---- Synthetic inputs (device; for benchmarks and tests) ----
  * Key i of a key set = SplitMix64 output i of the stream seeded seed

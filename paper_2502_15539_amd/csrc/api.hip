@@ -1,11 +1,13 @@
 // C ABI of the query library: handles, parameter rule, validation, device
 // residency of an MPHF and kernel dispatch. All compute happens in the HIP
 // kernels; this layer only checks arguments and launches.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -139,8 +141,79 @@ int check_params(const ptrhash_params *p) {
 
 }  // namespace
 
+namespace {
+
+MultiSpan span_of(const void *p, uint64_t bytes, int batch) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    return MultiSpan{a, a + bytes, batch};
+}
+
+// The input byte ranges a batch reads.
+int batch_inputs(const ptrhash_query_desc &d, int i, MultiSpan *in) {
+    if (d.handle->params.key_kind == PTRHASH_KEY_U64) {
+        in[0] = span_of(d.keys, d.n_q * sizeof(uint64_t), i);
+        return 1;
+    }
+    in[0] = span_of(d.data, d.data_len, i);
+    in[1] = span_of(d.offsets, (d.n_q + 1) * sizeof(uint64_t), i);
+    return 2;
+}
+
+// No batch's output range overlaps another output or any batch's input:
+// the outputs are sorted by start and must be disjoint; then each input is
+// checked against the last output that starts before it ends (outputs are
+// disjoint, so their ends ascend with their starts). outs: room for k spans.
+int check_batch_overlaps(const ptrhash_query_desc *descs, int k, MultiSpan *outs) {
+    int no = 0;
+    for (int i = 0; i < k; ++i)
+        if (descs[i].n_q)
+            outs[no++] = span_of(descs[i].out, descs[i].n_q * (descs[i].handle->params.index_bits / 8), i);
+    std::sort(outs, outs + no, [](const MultiSpan &a, const MultiSpan &b) { return a.lo < b.lo; });
+    for (int j = 1; j < no; ++j)
+        if (outs[j].lo < outs[j - 1].hi)
+            return fail(PTRHASH_E_INVAL, "batches %d and %d: outputs overlap", outs[j - 1].batch, outs[j].batch);
+    for (int i = 0; i < k; ++i) {
+        if (!descs[i].n_q) continue;
+        MultiSpan in[2];
+        const int m = batch_inputs(descs[i], i, in);
+        for (int r = 0; r < m; ++r) {
+            const MultiSpan *it = std::lower_bound(outs, outs + no, in[r].hi,
+                                                   [](const MultiSpan &o, uintptr_t end) { return o.lo < end; });
+            if (it != outs && (it - 1)->hi > in[r].lo)
+                return fail(PTRHASH_E_INVAL, "batch %d: an input overlaps the output of batch %d", i, (it - 1)->batch);
+        }
+    }
+    return PTRHASH_OK;
+}
+
+// Slot of handle h in the open-addressing table of w (inserted with index
+// `next` if absent; *fresh tells which).
+uint32_t handle_slot(MultiWork &w, const ptrhash_handle *h, uint32_t next, bool *fresh) {
+    const uint32_t mask = w.hcap - 1;
+    uint32_t i = (uint32_t)((reinterpret_cast<uintptr_t>(h) >> 4) * 0x9E3779B97F4A7C15ull >> 40) & mask;
+    while (w.handles[i] && w.handles[i] != h) i = (i + 1) & mask;
+    *fresh = !w.handles[i];
+    if (*fresh) {
+        w.handles[i] = h;
+        w.index[i] = next;
+    }
+    return w.index[i];
+}
+
+}  // namespace
+
 namespace ptrhash {
 int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile) {
+    uint32_t cap = 2;
+    while (cap < 2u * (uint32_t)(k > 0 ? k : 1)) cap <<= 1;
+    std::vector<MultiSpan> outs((size_t)(k > 0 ? k : 1));
+    std::vector<const ptrhash_handle *> handles(cap);
+    std::vector<uint32_t> index(cap);
+    MultiWork w{outs.data(), handles.data(), index.data(), cap};
+    return fill_multi_table_ws(t, descs, k, tile, w);
+}
+
+int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile, MultiWork &w) {
     // validate everything before touching the table
     for (int i = 0; i < k; ++i) {
         const ptrhash_query_desc &d = descs[i];
@@ -154,7 +227,14 @@ int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint
             if (!d.data || !d.offsets) return fail(PTRHASH_E_INVAL, "batch %d: data/offsets is NULL", i);
             if (reinterpret_cast<uintptr_t>(d.data) & 7u)
                 return fail(PTRHASH_E_INVAL, "batch %d: data must be 8-byte aligned", i);
+            if (d.data_len < kBytesPadding)
+                return fail(PTRHASH_E_INVAL, "batch %d: data_len %llu is below the %llu bytes of padding", i,
+                            (unsigned long long)d.data_len, (unsigned long long)kBytesPadding);
         }
+    }
+    if (k > 1 || (k == 1 && descs[0].n_q)) {
+        const int rc = check_batch_overlaps(descs, k, w.outs);
+        if (rc) return rc;
     }
     uint32_t c = 0;
     for (int i = 0; i < k; ++i) c += descs[i].n_q != 0;
@@ -162,26 +242,24 @@ int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint
     uint64_t *tb = multi_tile_begin(t);
     MultiBatch *bt = multi_batches(t);
     DevMphf *mp = multi_mphfs(t);
-    // each distinct handle once; requests for the same MPHF usually repeat
-    // the previous handle, so a small map of recent handles is enough
-    std::unordered_map<const ptrhash_handle *, uint32_t> index;
+    // each distinct handle once
+    for (uint32_t i = 0; i < w.hcap; ++i) w.handles[i] = nullptr;
     uint32_t j = 0, mphfs = 0;
     uint64_t tiles = 0;
     for (int i = 0; i < k; ++i) {
         const ptrhash_query_desc &d = descs[i];
         if (d.n_q == 0) continue;
-        auto it = index.find(d.handle);
-        if (it == index.end()) {
-            it = index.emplace(d.handle, mphfs).first;
-            mp[mphfs++] = device_view(d.handle);
-        }
+        bool fresh = false;
+        const uint32_t mi = handle_slot(w, d.handle, mphfs, &fresh);
+        if (fresh) mp[mphfs++] = device_view(d.handle);
         const bool bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
         MultiBatch &b = bt[j];
         b.keys = bytes ? static_cast<const void *>(d.data) : static_cast<const void *>(d.keys);
         b.offsets = bytes ? d.offsets : nullptr;
         b.out = d.out;
         b.nq = d.n_q;
-        b.mphf = it->second;
+        b.end_limit = bytes ? bytes_end_limit(d.data_len) : 0;
+        b.mphf = mi;
         b.flags = (bytes ? kBatchBytes : 0u) | (d.handle->params.index_bits == 64 ? kBatchOut64 : 0u);
         tb[j++] = tiles;
         tiles += (d.n_q + tile - 1) / tile;
@@ -394,9 +472,11 @@ PTRHASH_API int ptrhash_set_occupancy(ptrhash_handle *h, int blocks_per_cu, int 
     return PTRHASH_OK;
 }
 
+// The benchmark kernels run as one launch: its work-items (the grid times
+// the block) must stay below 2^32.
 static int check_grid(uint64_t n_q, const Tuning &t) {
     const uint64_t per_block = (uint64_t)t.block * (t.kernel == kKernelPlain ? 1 : t.keys_per_lane);
-    if ((n_q + per_block - 1) / per_block > 0x7fffffffull)
+    if ((n_q + per_block - 1) / per_block * (uint64_t)t.block > 0xffffffffull)
         return fail(PTRHASH_E_RANGE, "n_q %llu too large for one launch", (unsigned long long)n_q);
     return PTRHASH_OK;
 }
@@ -408,25 +488,32 @@ PTRHASH_API int ptrhash_query(ptrhash_handle *h, const uint64_t *keys, uint64_t 
     if (h->params.key_kind != PTRHASH_KEY_U64) return fail(PTRHASH_E_STATE, "MPHF is for byte keys");
     if (n_q == 0) return PTRHASH_OK;
     if (!keys || !out) return fail(PTRHASH_E_INVAL, "keys/out is NULL");
-    const int rc = check_grid(n_q, h->tuning);
-    if (rc) return rc;
+    if (n_q > (~0ull >> 4)) return fail(PTRHASH_E_RANGE, "n_q %llu too large", (unsigned long long)n_q);
+    if (ranges_overlap(keys, n_q * sizeof(uint64_t), out, n_q * (h->params.index_bits / 8)))
+        return fail(PTRHASH_E_INVAL, "keys and out overlap");
     const hipError_t e =
         launch_query_u64(device_view(h), keys, n_q, out, h->params.index_bits == 64, h->tuning, stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query launch");
 }
 
-PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, const uint64_t *offsets,
-                                    uint64_t n_q, void *out, hipStream_t stream) {
+PTRHASH_API int ptrhash_query_bytes(ptrhash_handle *h, const uint8_t *data, uint64_t data_len,
+                                    const uint64_t *offsets, uint64_t n_q, void *out, hipStream_t stream) {
     if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
     if (!h->loaded) return fail(PTRHASH_E_STATE, "handle has no MPHF loaded");
     if (h->params.key_kind != PTRHASH_KEY_BYTES) return fail(PTRHASH_E_STATE, "MPHF is for u64 keys");
     if (n_q == 0) return PTRHASH_OK;
     if (!data || !offsets || !out) return fail(PTRHASH_E_INVAL, "data/offsets/out is NULL");
     if (reinterpret_cast<uintptr_t>(data) & 7u) return fail(PTRHASH_E_INVAL, "data must be 8-byte aligned");
-    const int rc = check_grid(n_q, h->tuning);
-    if (rc) return rc;
-    const hipError_t e = launch_query_bytes(device_view(h), data, offsets, n_q, out, h->params.index_bits == 64,
-                                            h->tuning, stream);
+    if (data_len < kBytesPadding)
+        return fail(PTRHASH_E_INVAL, "data_len %llu is below the %llu bytes of padding", (unsigned long long)data_len,
+                    (unsigned long long)kBytesPadding);
+    if (n_q > (~0ull >> 4)) return fail(PTRHASH_E_RANGE, "n_q %llu too large", (unsigned long long)n_q);
+    const uint64_t out_bytes = n_q * (h->params.index_bits / 8);
+    if (ranges_overlap(data, data_len, out, out_bytes) ||
+        ranges_overlap(offsets, (n_q + 1) * sizeof(uint64_t), out, out_bytes))
+        return fail(PTRHASH_E_INVAL, "out overlaps data or offsets");
+    const hipError_t e = launch_query_bytes(device_view(h), data, bytes_end_limit(data_len), offsets, n_q, out,
+                                            h->params.index_bits == 64, h->tuning, stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query_bytes launch");
 }
 
@@ -593,6 +680,55 @@ PTRHASH_API int ptrhash_bench_gather(const uint64_t *keys, uint64_t n_q, const u
     const hipError_t e = launch_bench_gather(keys, n_q, table, table_len, out, keys_per_lane, block, t.lds_bytes,
                                              stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "gather launch");
+}
+
+PTRHASH_API int ptrhash_bench_gather_buckets(ptrhash_handle *h, const uint64_t *keys, uint64_t n_q, uint64_t *out,
+                                             int keys_per_lane, int block, int blocks_per_cu, hipStream_t stream) {
+    if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
+    if (!h->loaded) return fail(PTRHASH_E_STATE, "handle has no MPHF loaded");
+    if (h->params.key_kind != PTRHASH_KEY_U64) return fail(PTRHASH_E_STATE, "MPHF is for byte keys");
+    if (!valid_tuning(kKernelPipelined, keys_per_lane, block)) return fail(PTRHASH_E_INVAL, "bad tuning");
+    if (n_q == 0) return PTRHASH_OK;
+    if (!keys || !out) return fail(PTRHASH_E_INVAL, "NULL argument");
+    if (ranges_overlap(keys, n_q * 8, out, n_q * 8)) return fail(PTRHASH_E_INVAL, "keys and out overlap");
+    Tuning t{kKernelPipelined, keys_per_lane, block};
+    int rc = occupancy_lds(blocks_per_cu, &t.lds_bytes, nullptr);
+    if (rc) return rc;
+    rc = check_grid(n_q, t);
+    if (rc) return rc;
+    const hipError_t e = launch_bench_gather_bucket(keys, n_q, device_view(h), out, keys_per_lane, block, t.lds_bytes,
+                                                    stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "bucket gather launch");
+}
+
+PTRHASH_API int ptrhash_bench_gather_bytes(ptrhash_handle *h, const uint8_t *data, uint64_t data_len,
+                                           const uint64_t *offsets, uint64_t n_q, uint32_t *out, int keys_per_lane,
+                                           int block, int blocks_per_cu, hipStream_t stream) {
+    if (!h) return fail(PTRHASH_E_INVAL, "handle is NULL");
+    if (!h->loaded) return fail(PTRHASH_E_STATE, "handle has no MPHF loaded");
+    if (!valid_tuning(kKernelPipelined, keys_per_lane, block)) return fail(PTRHASH_E_INVAL, "bad tuning");
+    if (n_q == 0) return PTRHASH_OK;
+    if (!data || !offsets || !out) return fail(PTRHASH_E_INVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(data) & 7u) return fail(PTRHASH_E_INVAL, "data must be 8-byte aligned");
+    if (data_len < kBytesPadding) return fail(PTRHASH_E_INVAL, "data_len is below the padding");
+    if (ranges_overlap(data, data_len, out, n_q * 4) || ranges_overlap(offsets, (n_q + 1) * 8, out, n_q * 4))
+        return fail(PTRHASH_E_INVAL, "out overlaps data or offsets");
+    Tuning t{kKernelPipelined, keys_per_lane, block};
+    int rc = occupancy_lds(blocks_per_cu, &t.lds_bytes, nullptr);
+    if (rc) return rc;
+    rc = check_grid(n_q, t);
+    if (rc) return rc;
+    const hipError_t e = launch_bench_gather_bytes(data, bytes_end_limit(data_len), offsets, n_q, device_view(h), out,
+                                                   keys_per_lane, block, t.lds_bytes, stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "string gather launch");
+}
+
+PTRHASH_API int ptrhash_bench_scatter(const uint64_t *in, uint32_t log2_n, uint64_t *out, hipStream_t stream) {
+    if (!in || !out) return fail(PTRHASH_E_INVAL, "NULL argument");
+    if (log2_n < 8 || log2_n > 34) return fail(PTRHASH_E_INVAL, "log2_n must be 8..34");
+    if (ranges_overlap(in, 8ull << log2_n, out, 8ull << log2_n)) return fail(PTRHASH_E_INVAL, "in and out overlap");
+    const hipError_t e = launch_bench_scatter(in, log2_n, out, stream);
+    return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "scatter launch");
 }
 
 PTRHASH_API int ptrhash_bench_gather_pure(uint64_t n, const uint8_t *table, uint64_t table_len, uint32_t *sink,

@@ -32,12 +32,13 @@ bool valid_multi_tuning(int keys_per_lane, int block, int blocks_per_cu);
 inline uint32_t multi_tile(const MultiTuning &t) { return (uint32_t)t.keys_per_lane * (uint32_t)t.block; }
 MultiTuning multi_default_tuning();  // the process-wide default (ptrhash_set_multi_kernel)
 
-// One batch of a multi-MPHF launch (40 bytes).
+// One batch of a multi-MPHF launch (48 bytes).
 struct MultiBatch {
     const void *keys;         // u64 keys, or the packed bytes of byte keys
     const uint64_t *offsets;  // byte keys: nq + 1 offsets into keys
     void *out;
     uint64_t nq;
+    uint64_t end_limit;       // byte keys: largest string end offset that can be read safely
     uint32_t mphf;            // index into the table's MPHF array
     uint32_t flags;           // kBatchBytes | kBatchOut64
 };
@@ -55,7 +56,7 @@ struct MultiTable {
     uint32_t mphfs;  // distinct MPHFs
     uint32_t pad_[3];
 };
-static_assert(sizeof(MultiTable) == 32 && sizeof(MultiBatch) == 40, "multi table layout");
+static_assert(sizeof(MultiTable) == 32 && sizeof(MultiBatch) == 48, "multi table layout");
 
 __host__ __device__ inline uint64_t *multi_tile_begin(MultiTable *t) { return reinterpret_cast<uint64_t *>(t + 1); }
 __host__ __device__ inline const uint64_t *multi_tile_begin(const MultiTable *t) {
@@ -92,10 +93,40 @@ uint32_t multi_grid(const MultiTuning &t);      // persistent grid size on the c
 // `tile` keys) into t.
 int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile);
 
+// The same with a caller-provided host workspace, so that the fill itself
+// allocates nothing: room for k output spans, and an open-addressing table
+// of hcap handle slots (hcap a power of two, at least 2k).
+struct MultiSpan {
+    uintptr_t lo, hi;  // [lo, hi)
+    int batch;
+};
+struct MultiWork {
+    MultiSpan *outs;
+    const ptrhash_handle **handles;
+    uint32_t *index;
+    uint32_t hcap;
+};
+int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile, MultiWork &w);
+
 hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
                             const Tuning &t, hipStream_t s);
-hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
-                              void *out, bool out64, const Tuning &t, hipStream_t s);
+// Byte keys: a string may end at most at end_limit (see bytes_end_limit);
+// a key whose offsets decrease or pass it is not read and gets an index of
+// all ones.
+hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, uint64_t end_limit, const uint64_t *offsets,
+                              uint64_t nq, void *out, bool out64, const Tuning &t, hipStream_t s);
+
+// The string hash reads aligned 8-byte words up to 15 bytes past a string's
+// end, so a string in a buffer of data_len bytes may end at data_len - 16.
+constexpr uint64_t kBytesReadSlack = 16;
+constexpr uint64_t kBytesPadding = 64;  // readable bytes the ABI asks for after the last string
+inline uint64_t bytes_end_limit(uint64_t data_len) { return data_len - kBytesReadSlack; }
+
+// [a, a + na) and [b, b + nb) share a byte.
+inline bool ranges_overlap(const void *a, uint64_t na, const void *b, uint64_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na && nb && x < y + nb && y < x + na;
+}
 
 hipError_t launch_bench_gather(const uint64_t *keys, uint64_t nq, const uint8_t *table, uint64_t table_len,
                                uint64_t *out, int keys_per_lane, int block, uint32_t lds_bytes, hipStream_t s);
@@ -105,5 +136,11 @@ hipError_t launch_bench_gather_pair(uint64_t n, const uint8_t *table, uint64_t T
                                     uint32_t grid, hipStream_t s);
 hipError_t launch_bench_copy(const uint64_t *keys, uint64_t nq, uint64_t *out, int keys_per_lane, int block,
                              hipStream_t s);
+hipError_t launch_bench_gather_bucket(const uint64_t *keys, uint64_t nq, const DevMphf &m, uint64_t *out,
+                                      int keys_per_lane, int block, uint32_t lds_bytes, hipStream_t s);
+hipError_t launch_bench_gather_bytes(const uint8_t *data, uint64_t end_limit, const uint64_t *offsets, uint64_t nq,
+                                     const DevMphf &m, uint32_t *out, int keys_per_lane, int block,
+                                     uint32_t lds_bytes, hipStream_t s);
+hipError_t launch_bench_scatter(const uint64_t *in, uint32_t log2_n, uint64_t *out, hipStream_t s);
 
 }  // namespace ptrhash

@@ -73,23 +73,27 @@ __device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], con
 }
 
 // One tile of K*stride keys starting at base: lane tid handles keys
-// base + tid + j*stride, j < K. Bytes selects packed byte-string keys.
+// base + tid + j*stride, j < K. Bytes selects packed byte-string keys; a
+// string may end at most at end_limit, and one whose offsets decrease or
+// pass that limit is not read and gets an index of all ones.
 template <int K, typename OutT, bool Bytes>
 __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *__restrict__ keys,
                                              const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets,
-                                             uint64_t nq, OutT *__restrict__ out, uint64_t base, uint32_t stride) {
+                                             uint64_t end_limit, uint64_t nq, OutT *__restrict__ out, uint64_t base,
+                                             uint32_t stride) {
     uint64_t h[K], hs[K];  // hash for part/bucket, hash for the slot
-    bool ok[K];
+    bool ok[K], bad[K];
     if (Bytes) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint64_t i = base + (uint64_t)j * stride;
             ok[j] = i < nq;
+            bad[j] = false;
+            h[j] = hs[j] = 0;
             if (ok[j]) {
                 const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
-                h[j] = hash_bytes(m.seed, data, o0, o1 - o0, m.hash128 != 0, hs[j]);
-            } else {
-                h[j] = hs[j] = 0;
+                bad[j] = o1 < o0 || o1 > end_limit;
+                if (!bad[j]) h[j] = hash_bytes(m.seed, data, o0, o1 - o0, m.hash128 != 0, hs[j]);
             }
         }
     } else {
@@ -102,6 +106,7 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
         for (int j = 0; j < K; ++j) {
             const uint64_t i = base + (uint64_t)j * stride;
             ok[j] = i < nq;
+            bad[j] = false;
             key[j] = nt_load(keys + (ok[j] ? i : 0));
         }
 #pragma unroll
@@ -119,7 +124,7 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * stride;
-        if (ok[j]) nt_store((OutT)v[j], out + i);
+        if (ok[j]) nt_store(Bytes && bad[j] ? (OutT)~0ull : (OutT)v[j], out + i);
     }
 }
 
@@ -127,15 +132,15 @@ template <int K, typename OutT>
 __global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restrict__ keys, uint64_t nq,
                                                         OutT *__restrict__ out, DevMphf m) {
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    process_tile<K, OutT, false>(m, keys, nullptr, nullptr, nq, out, base, blockDim.x);
+    process_tile<K, OutT, false>(m, keys, nullptr, nullptr, 0, nq, out, base, blockDim.x);
 }
 
 template <int K, typename OutT>
-__global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict__ data,
+__global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict__ data, uint64_t end_limit,
                                                       const uint64_t *__restrict__ offsets, uint64_t nq,
                                                       OutT *__restrict__ out, DevMphf m) {
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    process_tile<K, OutT, true>(m, nullptr, data, offsets, nq, out, base, blockDim.x);
+    process_tile<K, OutT, true>(m, nullptr, data, offsets, end_limit, nq, out, base, blockDim.x);
 }
 
 // Persistent launch over a table of query batches (each against its own
@@ -167,19 +172,19 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
         if (q.flags & kBatchBytes) {
             const uint8_t *data = static_cast<const uint8_t *>(q.keys);
             if (q.flags & kBatchOut64)
-                process_tile<K, uint64_t, true>(m, nullptr, data, q.offsets, q.nq, static_cast<uint64_t *>(q.out), base,
-                                                blockDim.x);
+                process_tile<K, uint64_t, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
+                                                static_cast<uint64_t *>(q.out), base, blockDim.x);
             else
-                process_tile<K, uint32_t, true>(m, nullptr, data, q.offsets, q.nq, static_cast<uint32_t *>(q.out), base,
-                                                blockDim.x);
+                process_tile<K, uint32_t, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
+                                                static_cast<uint32_t *>(q.out), base, blockDim.x);
         } else {
             const uint64_t *keys = static_cast<const uint64_t *>(q.keys);
             if (q.flags & kBatchOut64)
-                process_tile<K, uint64_t, false>(m, keys, nullptr, nullptr, q.nq, static_cast<uint64_t *>(q.out), base,
-                                                 blockDim.x);
+                process_tile<K, uint64_t, false>(m, keys, nullptr, nullptr, 0, q.nq, static_cast<uint64_t *>(q.out),
+                                                 base, blockDim.x);
             else
-                process_tile<K, uint32_t, false>(m, keys, nullptr, nullptr, q.nq, static_cast<uint32_t *>(q.out), base,
-                                                 blockDim.x);
+                process_tile<K, uint32_t, false>(m, keys, nullptr, nullptr, 0, q.nq, static_cast<uint32_t *>(q.out),
+                                                 base, blockDim.x);
         }
     }
 }
@@ -188,33 +193,45 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
 
 static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// A dispatch holds fewer than 2^32 work-items (grid times block), so a large
+// batch is split into launches of at most 2^31 / block workgroups each, one
+// after the other on the same stream.
+static inline uint64_t keys_per_launch(uint32_t block, int K) {
+    return (uint64_t)(0x80000000u / block) * block * (uint64_t)K;
+}
+
 template <typename OutT>
 static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, const Tuning &t,
                                hipStream_t s) {
     OutT *o = static_cast<OutT *>(out);
     const uint32_t blk = (uint32_t)t.block;
-    if (t.kernel == kKernelPlain) {
-        hipLaunchKernelGGL(query_plain<OutT>, dim3((uint32_t)ceil_div(nq, blk)), dim3(blk), t.lds_bytes, s, keys, nq,
-                           o, m);
-        return hipGetLastError();
-    }
-    const uint64_t grid = ceil_div(nq, (uint64_t)blk * t.keys_per_lane);
-    switch (t.keys_per_lane) {
-#define PTRHASH_CASE(KK)                                                                                     \
-    case KK:                                                                                                 \
-        hipLaunchKernelGGL((query_pipelined<KK, OutT>), dim3((uint32_t)grid), dim3(blk), t.lds_bytes, s, keys, nq, o, \
-                           m);                                                                             \
+    const int K = t.kernel == kKernelPlain ? 1 : t.keys_per_lane;
+    const uint64_t chunk = keys_per_launch(blk, K);
+    for (uint64_t s0 = 0; s0 < nq; s0 += chunk) {
+        const uint64_t n = nq - s0 < chunk ? nq - s0 : chunk;
+        const dim3 grid((uint32_t)ceil_div(n, (uint64_t)blk * K));
+        if (t.kernel == kKernelPlain) {
+            hipLaunchKernelGGL(query_plain<OutT>, grid, dim3(blk), t.lds_bytes, s, keys + s0, n, o + s0, m);
+        } else {
+            switch (K) {
+#define PTRHASH_CASE(KK)                                                                                      \
+    case KK:                                                                                                  \
+        hipLaunchKernelGGL((query_pipelined<KK, OutT>), grid, dim3(blk), t.lds_bytes, s, keys + s0, n, o + s0, m); \
         break;
-        PTRHASH_CASE(1)
-        PTRHASH_CASE(2)
-        PTRHASH_CASE(4)
-        PTRHASH_CASE(8)
-        PTRHASH_CASE(16)
+                PTRHASH_CASE(1)
+                PTRHASH_CASE(2)
+                PTRHASH_CASE(4)
+                PTRHASH_CASE(8)
+                PTRHASH_CASE(16)
 #undef PTRHASH_CASE
-    default:
-        return hipErrorInvalidValue;
+            default:
+                return hipErrorInvalidValue;
+            }
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, bool out64,
@@ -223,34 +240,40 @@ hipError_t launch_query_u64(const DevMphf &m, const uint64_t *keys, uint64_t nq,
 }
 
 template <typename OutT>
-static hipError_t launch_bytes_t(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
-                                 void *out, const Tuning &t, hipStream_t s) {
+static hipError_t launch_bytes_t(const DevMphf &m, const uint8_t *data, uint64_t end_limit, const uint64_t *offsets,
+                                 uint64_t nq, void *out, const Tuning &t, hipStream_t s) {
     OutT *o = static_cast<OutT *>(out);
     const uint32_t blk = (uint32_t)t.block;
     const int K = t.kernel == kKernelPlain ? 1 : t.keys_per_lane;
-    const uint64_t grid = ceil_div(nq, (uint64_t)blk * K);
-    switch (K) {
-#define PTRHASH_CASE(KK)                                                                                   \
-    case KK:                                                                                               \
-        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), dim3((uint32_t)grid), dim3(blk), t.lds_bytes, s, data, offsets, nq, \
-                           o, m);                                                                          \
+    const uint64_t chunk = keys_per_launch(blk, K);
+    for (uint64_t s0 = 0; s0 < nq; s0 += chunk) {
+        const uint64_t n = nq - s0 < chunk ? nq - s0 : chunk;
+        const dim3 grid((uint32_t)ceil_div(n, (uint64_t)blk * K));
+        switch (K) {
+#define PTRHASH_CASE(KK)                                                                                      \
+    case KK:                                                                                                  \
+        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), grid, dim3(blk), t.lds_bytes, s, data, end_limit,       \
+                           offsets + s0, n, o + s0, m);                                                       \
         break;
-        PTRHASH_CASE(1)
-        PTRHASH_CASE(2)
-        PTRHASH_CASE(4)
-        PTRHASH_CASE(8)
-        PTRHASH_CASE(16)
+            PTRHASH_CASE(1)
+            PTRHASH_CASE(2)
+            PTRHASH_CASE(4)
+            PTRHASH_CASE(8)
+            PTRHASH_CASE(16)
 #undef PTRHASH_CASE
-    default:
-        return hipErrorInvalidValue;
+        default:
+            return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
-hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, const uint64_t *offsets, uint64_t nq,
-                              void *out, bool out64, const Tuning &t, hipStream_t s) {
-    return out64 ? launch_bytes_t<uint64_t>(m, data, offsets, nq, out, t, s)
-                 : launch_bytes_t<uint32_t>(m, data, offsets, nq, out, t, s);
+hipError_t launch_query_bytes(const DevMphf &m, const uint8_t *data, uint64_t end_limit, const uint64_t *offsets,
+                              uint64_t nq, void *out, bool out64, const Tuning &t, hipStream_t s) {
+    return out64 ? launch_bytes_t<uint64_t>(m, data, end_limit, offsets, nq, out, t, s)
+                 : launch_bytes_t<uint32_t>(m, data, end_limit, offsets, nq, out, t, s);
 }
 
 template <typename F>

@@ -189,9 +189,52 @@ struct StatWindow {
     }
 };
 
+// Device-timeline intervals of recent launches (ms after the server's base
+// event), for the overlap metrics.
+constexpr size_t kSpanWindow = size_t(1) << 16;
+struct SpanWindow {
+    std::vector<std::pair<double, double>> v;
+    size_t next = 0;
+    void add(double a, double b) {
+        if (v.size() < kSpanWindow) {
+            v.emplace_back(a, b);
+        } else {
+            v[next] = {a, b};
+            next = (next + 1) % kSpanWindow;
+        }
+    }
+    void clear() {
+        v.clear();
+        next = 0;
+    }
+    // Most intervals open at one instant, and the mean number open over the
+    // time at least one is (sum of lengths / length of their union).
+    void overlap(uint64_t &most, double &mean) const {
+        std::vector<std::pair<double, int>> ev;
+        ev.reserve(2 * v.size());
+        for (const auto &iv : v) {
+            ev.emplace_back(iv.first, +1);
+            ev.emplace_back(iv.second, -1);
+        }
+        std::sort(ev.begin(), ev.end());  // an end sorts before a start at the same instant
+        int open = 0, top = 0;
+        double busy = 0, total = 0, prev = 0;
+        for (const auto &e : ev) {
+            if (open > 0) busy += e.first - prev;
+            open += e.second;
+            if (open > top) top = open;
+            prev = e.first;
+        }
+        for (const auto &iv : v) total += iv.second - iv.first;
+        most = (uint64_t)top;
+        mean = busy > 0 ? total / busy : (v.empty() ? 0.0 : 1.0);
+    }
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t start = nullptr;  // recorded before the slot's launch (timing events)
+    hipEvent_t done = nullptr;   // recorded after it
     ptrhash_multi_plan *plan = nullptr;        // copy mode
     uint64_t *d_keys = nullptr, *h_keys = nullptr;
     uint8_t *d_out = nullptr, *h_out = nullptr;
@@ -217,8 +260,11 @@ struct ptrhash_server {
     std::unordered_map<uint64_t, double> finished;  // ticket -> latency (us), until waited for
     StatWindow latencies;                            // completed requests (recent ones)
     StatWindow waits;                                // submit -> launch enqueued
+    SpanWindow spans;                                // device start/done of recent launches
+    hipEvent_t base = nullptr;                       // time origin of the spans
     CopyPool *pool = nullptr;
     uint64_t launches = 0, completed = 0, keys_done = 0;
+    int busy_now = 0, busy_max = 0;                  // slots launched and not yet retired
     int error = PTRHASH_OK;
     bool stop = false;
     int device = 0;
@@ -240,6 +286,7 @@ void free_slot(Slot &s) {
     if (s.h_keys) (void)hipHostFree(s.h_keys);
     if (s.h_out) (void)hipHostFree(s.h_out);
     if (s.h_table) (void)hipHostFree(s.h_table);
+    if (s.start) (void)hipEventDestroy(s.start);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     s = Slot{};
@@ -252,7 +299,12 @@ void retire(ptrhash_server *srv, Slot &s) {
         if (!r.mapped) add_copy(jobs, r.out, s.h_out + r.out_off, r.n_q * r.out_bytes);
     srv->pool->run(jobs);
     const auto now = Clock::now();
+    float t0 = 0, t1 = 0;
+    const bool timed = hipEventElapsedTime(&t0, srv->base, s.start) == hipSuccess &&
+                       hipEventElapsedTime(&t1, srv->base, s.done) == hipSuccess;
     std::lock_guard<std::mutex> lock(srv->mu);
+    if (timed) srv->spans.add(t0, t1);
+    srv->busy_now--;
     for (const Request &r : s.reqs) {
         srv->waits.add(std::chrono::duration<double, std::micro>(r.t_launch - r.t_submit).count());
         const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
@@ -287,6 +339,7 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
     }
     if (s.reqs.empty()) return PTRHASH_OK;
     s.busy = true;
+    if (++srv->busy_now > srv->busy_max) srv->busy_max = srv->busy_now;
     lock.unlock();
     const bool zc = srv->cfg.zero_copy != 0;
     std::vector<ptrhash_query_desc> descs(s.reqs.size());
@@ -294,28 +347,31 @@ int admit(ptrhash_server *srv, Slot &s, std::unique_lock<std::mutex> &lock) {
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         const Request &r = s.reqs[i];
         if (r.mapped) {
-            descs[i] = ptrhash_query_desc{r.handle, r.v_keys, nullptr, nullptr, r.n_q, r.v_out};
+            descs[i] = ptrhash_query_desc{r.handle, r.v_keys, nullptr, 0, nullptr, r.n_q, r.v_out};
             continue;
         }
         add_copy(jobs, s.h_keys + r.key_off, r.keys, r.n_q * sizeof(uint64_t));
         uint64_t *k = (zc ? s.v_keys : s.d_keys) + r.key_off;
         uint8_t *o = (zc ? s.v_out : s.d_out) + r.out_off;
-        descs[i] = ptrhash_query_desc{r.handle, k, nullptr, nullptr, r.n_q, o};
+        descs[i] = ptrhash_query_desc{r.handle, k, nullptr, 0, nullptr, r.n_q, o};
     }
     srv->pool->run(jobs);
     int rc;
     hipError_t e = hipSuccess;
     if (zc) {
         // the kernel reads keys and the batch table from, and writes indices
-        // to, mapped coherent host memory: one stream operation per launch
+        // to, mapped coherent host memory: one kernel per launch
         rc = ptrhash::fill_multi_table(s.h_table, descs.data(), (int)descs.size(), ptrhash::multi_tile(srv->tuning));
         if (rc == PTRHASH_OK) {
-            e = ptrhash::launch_query_multi(s.v_table, srv->tuning, srv->grid, s.stream);
+            e = hipEventRecord(s.start, s.stream);
+            if (e == hipSuccess) e = ptrhash::launch_query_multi(s.v_table, srv->tuning, srv->grid, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
             if (e != hipSuccess) rc = hip_err(e, "serving launch");
         }
     } else if ((rc = ptrhash_multi_plan_set(s.plan, descs.data(), (int)descs.size())) == PTRHASH_OK) {
-        if (used) e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+        e = hipEventRecord(s.start, s.stream);
+        if (e == hipSuccess && used)
+            e = hipMemcpyAsync(s.d_keys, s.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) rc = ptrhash_multi_plan_launch(s.plan, s.stream);
         if (e == hipSuccess && rc == PTRHASH_OK && out_used)
             e = hipMemcpyAsync(s.h_out, s.d_out, out_used, hipMemcpyDeviceToHost, s.stream);
@@ -435,7 +491,7 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
         const uint64_t kb = cfg->slot_keys * sizeof(uint64_t);
         const uint64_t ob = cfg->slot_keys * sizeof(uint64_t) + 8 * (uint64_t)cfg->max_batches;
         if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
+            (e = hipEventCreate(&s.start)) != hipSuccess || (e = hipEventCreate(&s.done)) != hipSuccess) {
             rc = hip_err(e, "stream/event creation");
             break;
         }
@@ -461,8 +517,15 @@ PTRHASH_API int ptrhash_server_create(const ptrhash_server_config *cfg, ptrhash_
                 rc = ptrhash_multi_plan_set_kernel(s.plan, tuning.keys_per_lane, tuning.block, tuning.blocks_per_cu);
         }
     }
+    if (rc == PTRHASH_OK) {
+        if ((e = hipEventCreate(&srv->base)) != hipSuccess ||
+            (e = hipEventRecord(srv->base, srv->slots[0].stream)) != hipSuccess ||
+            (e = hipEventSynchronize(srv->base)) != hipSuccess)
+            rc = hip_err(e, "server base event");
+    }
     if (rc) {
         for (Slot &s : srv->slots) free_slot(s);
+        if (srv->base) (void)hipEventDestroy(srv->base);
         delete srv;
         return rc;
     }
@@ -593,6 +656,8 @@ PTRHASH_API int ptrhash_server_stats(ptrhash_server *srv, ptrhash_server_metrics
     auto wp = [&](double q) { return w.empty() ? 0.0 : w[std::min(w.size() - 1, (size_t)(q * (w.size() - 1) + 0.5))]; };
     st->wait_p50_us = wp(0.50);
     st->wait_p99_us = wp(0.99);
+    st->slots_busy_max = (uint64_t)srv->busy_max;
+    srv->spans.overlap(st->overlap_max, st->overlap_mean);
     return srv->error;
 }
 
@@ -601,6 +666,8 @@ PTRHASH_API int ptrhash_server_reset_stats(ptrhash_server *srv) {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->latencies.clear();
     srv->waits.clear();
+    srv->spans.clear();
+    srv->busy_max = srv->busy_now;
     srv->completed = srv->launches = srv->keys_done = 0;
     return PTRHASH_OK;
 }
@@ -644,6 +711,7 @@ PTRHASH_API int ptrhash_server_destroy(ptrhash_server *srv) {
         free_slot(s);
     }
     const int err = srv->error;
+    if (srv->base) (void)hipEventDestroy(srv->base);
     delete srv->pool;
     delete srv;
     return err;

@@ -4,13 +4,13 @@
         per-kernel calls / total / average duration (markdown)
     python -m paper_2502_15539_amd.profsum counters DB [DB ...]
         mean value of each collected counter per kernel (markdown)
-    python -m paper_2502_15539_amd.profsum traffic --fetch DB --write DB \\
-            --kernel SUBSTR (--copy SUBSTR --copy-bytes N | --scale-from JSON) --out JSON
-        HBM bytes per launch of a kernel from FETCH_SIZE and WRITE_SIZE, each
-        scaled by the factor that maps the same counter of a plain copy
-        kernel (reading and writing N bytes) onto N, or by the factors of an
-        earlier traffic JSON of the same device; the JSON records a hash of
-        the kernel sources so that a later change voids it.
+    python -m paper_2502_15539_amd.profsum traffic --reads DB --write DB --kernel SUBSTR --out JSON
+        Bytes per launch of a kernel between the L2 caches and the memory
+        fabric: read requests counted by size (TCC_EA0_RDREQ_<size>B_sum,
+        each times its size) plus WRITE_SIZE; DRAM read requests
+        (TCC_EA0_RDREQ_DRAM_sum) beside them, since reads served by the MALL
+        do not reach HBM. The JSON records a hash of the kernel sources so
+        that a later change voids it.
     python -m paper_2502_15539_amd.profsum valu --db DB --kernel SUBSTR --out JSON
         vector-ALU instructions per launch of a kernel (SQ_INSTS_VALU, counted
         per wavefront) with the VALUBusy and VALUUtilization metrics, and the
@@ -82,20 +82,24 @@ def _mean(db, kernel_sub, counter):
 
 
 def traffic(args) -> dict:
-    if args.scale_from:
-        ref = json.load(open(args.scale_from))
-        fs, ws = ref["fetch_scale"], ref["write_scale"]
-    else:
-        if not args.copy or not args.copy_bytes:
-            raise SystemExit("traffic needs --copy and --copy-bytes, or --scale-from")
-        copy_fetch = _mean(args.fetch, args.copy, "FETCH_SIZE") * 1024.0
-        copy_write = _mean(args.write, args.copy, "WRITE_SIZE") * 1024.0
-        fs, ws = args.copy_bytes / copy_fetch, args.copy_bytes / copy_write
-    k_fetch = _mean(args.fetch, args.kernel, "FETCH_SIZE") * 1024.0
+    reads = [(c, v) for k, c, v, _ in counter_means(args.reads) if args.kernel in k]
+    sized = {}
+    for c, v in reads:
+        m = re.fullmatch(r"TCC_EA0_RDREQ_(\d+)B_sum", c)
+        if m:
+            sized[int(m.group(1))] = v
+    if not sized:
+        raise SystemExit(f"no TCC_EA0_RDREQ_<size>B_sum counters for {args.kernel!r} in {args.reads}")
+    read_bytes = sum(size * v for size, v in sized.items())
     k_write = _mean(args.write, args.kernel, "WRITE_SIZE") * 1024.0
-    res = {"kernel": args.kernel, "fetch_bytes_raw": k_fetch, "write_bytes_raw": k_write,
-           "fetch_scale": fs, "write_scale": ws, "fetch_bytes": k_fetch * fs, "write_bytes": k_write * ws,
-           "traffic_bytes_per_launch": k_fetch * fs + k_write * ws, "kernel_source_sha256": kernel_source_hash()}
+    other = {c: v for c, v in reads if not re.fullmatch(r"TCC_EA0_RDREQ_(\d+)B_sum", c)}
+    res = {"kernel": args.kernel,
+           "level": "L2 to memory fabric: read requests by size plus WRITE_SIZE (includes MALL hits)",
+           "read_requests_by_size": {f"{k}B": v for k, v in sorted(sized.items())},
+           "read_bytes": read_bytes, "write_bytes": k_write,
+           "dram_read_requests": other.get("TCC_EA0_RDREQ_DRAM_sum"),
+           "read_requests": other.get("TCC_EA0_RDREQ_sum"),
+           "traffic_bytes_per_launch": read_bytes + k_write, "kernel_source_sha256": kernel_source_hash()}
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     return res
@@ -119,12 +123,9 @@ def main():
     c = sub.add_parser("counters")
     c.add_argument("dbs", nargs="+")
     r = sub.add_parser("traffic")
-    r.add_argument("--fetch", required=True)
-    r.add_argument("--write", required=True)
+    r.add_argument("--reads", required=True, help="DB with TCC_EA0_RDREQ_<size>B_sum (and _DRAM_sum) counters")
+    r.add_argument("--write", required=True, help="DB with WRITE_SIZE")
     r.add_argument("--kernel", required=True)
-    r.add_argument("--copy")
-    r.add_argument("--copy-bytes", type=float)
-    r.add_argument("--scale-from", help="take the scale factors of this traffic JSON")
     r.add_argument("--out", required=True)
     v = sub.add_parser("valu")
     v.add_argument("--db", required=True)

@@ -64,6 +64,7 @@ class QueryDesc(C.Structure):
         ("handle", C.c_void_p),
         ("keys", C.c_void_p),
         ("data", C.c_void_p),
+        ("data_len", C.c_uint64),
         ("offsets", C.c_void_p),
         ("n_q", C.c_uint64),
         ("out", C.c_void_p),
@@ -79,7 +80,8 @@ class ServerConfig(C.Structure):
 class ServerMetrics(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("launches", C.c_uint64), ("keys", C.c_uint64), ("queued", C.c_uint64),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double),
-                ("wait_p50_us", C.c_double), ("wait_p99_us", C.c_double)]
+                ("wait_p50_us", C.c_double), ("wait_p99_us", C.c_double), ("slots_busy_max", C.c_uint64),
+                ("overlap_max", C.c_uint64), ("overlap_mean", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,7 +110,8 @@ _SIGS = {
     "ptrhash_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Params)]),
     "ptrhash_get_params": (C.c_int, [C.c_void_p, C.POINTER(Params)]),
     "ptrhash_query": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
-    "ptrhash_query_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "ptrhash_query_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p,
+                                      C.c_void_p]),
     "ptrhash_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ptrhash_last_error": (C.c_char_p, []),
     "ptrhash_set_occupancy": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
@@ -135,6 +138,11 @@ _SIGS = {
     "ptrhash_bench_gather_pure": (C.c_int, [C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32,
                                             C.c_void_p]),
     "ptrhash_bench_copy": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "ptrhash_bench_gather_buckets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
+                                               C.c_int, C.c_void_p]),
+    "ptrhash_bench_gather_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p,
+                                             C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "ptrhash_bench_scatter": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "ptrhash_multi_plan_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "ptrhash_multi_plan_destroy": (C.c_int, [C.c_void_p]),
     "ptrhash_multi_plan_set": (C.c_int, [C.c_void_p, C.POINTER(QueryDesc), C.c_int]),
@@ -385,17 +393,26 @@ class Mphf:
         out = torch.empty(keys.numel(), dtype=dt, device=keys.device)
         return self.query_into(keys, out, stream)
 
-    def query_bytes_into(self, data, offsets, out, stream=None):
+    def query_bytes_into(self, data, offsets, out, stream=None, check_end=True):
         """data: cuda uint8 tensor of packed strings (8-byte aligned, 64 readable
         bytes after the last string); offsets: n + 1 u64 offsets; out: n
-        indices of index_bits width."""
+        indices of index_bits width. check_end reads offsets[n] back (one
+        synchronising 8-byte copy) and refuses a data tensor shorter than
+        offsets[n] + 64 bytes; the kernel itself never reads past data and
+        gives keys with bad offsets an index of all ones."""
         n = offsets.numel() - 1
         if n < 0:
             raise ValueError("offsets needs at least one entry")
         ob = self.index_bytes
-        _check(lib().ptrhash_query_bytes(self._h, _device_tensor(data, "data", 1, 0),
-                                         _device_tensor(offsets, "offsets", 8, n + 1), n,
-                                         _device_tensor(out, "out", ob, n), _stream(stream)), "ptrhash_query_bytes")
+        dp = _device_tensor(data, "data", 1, 0)
+        op = _device_tensor(offsets, "offsets", 8, n + 1)
+        if check_end and n > 0:
+            end = int(offsets[n].item())
+            if end < 0 or end + 64 > data.numel():
+                raise ValueError(f"data holds {data.numel()} bytes; the strings end at {end} and 64 bytes of "
+                                 "padding must follow")
+        _check(lib().ptrhash_query_bytes(self._h, dp, data.numel(), op, n, _device_tensor(out, "out", ob, n),
+                                         _stream(stream)), "ptrhash_query_bytes")
         return out
 
     def query_bytes(self, data, offsets, stream=None):
@@ -425,6 +442,30 @@ def bench_gather_pair(n, table, sink, xor_dist, stream=None):
     _check(lib().ptrhash_bench_gather_pair(int(n), _device_tensor(table, "table", 1, 1), table.numel(),
                                            _device_tensor(sink, "sink", 4, 0), sink.numel(), int(xor_dist),
                                            _stream(stream)), "ptrhash_bench_gather_pair")
+
+
+def bench_gather_buckets(mphf, keys, out, keys_per_lane=4, block=256, blocks_per_cu=0, stream=None):
+    """Like-for-like gather: each key's own pilot byte of a loaded u64-key MPHF."""
+    n = keys.numel()
+    _check(lib().ptrhash_bench_gather_buckets(mphf.handle, _device_tensor(keys, "keys", 8, n), n,
+                                              _device_tensor(out, "out", 8, n), int(keys_per_lane), int(block),
+                                              int(blocks_per_cu), _stream(stream)), "ptrhash_bench_gather_buckets")
+
+
+def bench_gather_bytes(mphf, data, offsets, out, keys_per_lane=1, block=256, blocks_per_cu=0, stream=None):
+    """String-stream gather: the memory pattern of a byte-key query (u32 out)."""
+    n = offsets.numel() - 1
+    _check(lib().ptrhash_bench_gather_bytes(mphf.handle, _device_tensor(data, "data", 1, 0), data.numel(),
+                                            _device_tensor(offsets, "offsets", 8, n + 1), n,
+                                            _device_tensor(out, "out", 4, n), int(keys_per_lane), int(block),
+                                            int(blocks_per_cu), _stream(stream)), "ptrhash_bench_gather_bytes")
+
+
+def bench_scatter(src, log2_n, out, stream=None):
+    """out[(i * A) mod 2^log2_n] = src[i]: the cost of an un-permute pass."""
+    n = 1 << int(log2_n)
+    _check(lib().ptrhash_bench_scatter(_device_tensor(src, "src", 8, n), int(log2_n), _device_tensor(out, "out", 8, n),
+                                       _stream(stream)), "ptrhash_bench_scatter")
 
 
 def bench_copy(keys, out, keys_per_lane=4, block=256, stream=None):
@@ -458,6 +499,7 @@ def make_descs(batches):
             data, offsets = keys
             d.n_q = offsets.numel() - 1
             d.data = _device_tensor(data, "data", 1, 0).value
+            d.data_len = data.numel()
             d.offsets = _device_tensor(offsets, "offsets", 8, d.n_q + 1).value
         else:
             d.n_q = keys.numel()

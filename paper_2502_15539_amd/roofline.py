@@ -12,6 +12,12 @@ streams) and, once, the stream copy (16 B per key). Prints one JSON object.
 second byte read at o xor D of every random offset o (D = 32, 64, 128): a
 second byte in the same 128-byte line costs nothing if a miss fills the
 whole line, and a second miss if it does not.
+
+--partition prices answering the 10^9-key stream part by part: the query
+over the same stream grouped by part (each part's 296 KB of pilots then
+stays in the L2), against the query over the shuffled stream, next to the
+un-permute that grouping would need (one random 8-byte write per index,
+2^30 of them) and the streaming copy (the least a partition pass costs).
 """
 from __future__ import annotations
 
@@ -31,9 +37,12 @@ def main():
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--reps", type=int, default=4)
     ap.add_argument("--lines", action="store_true", help="line-size probe instead of the size sweep")
+    ap.add_argument("--partition", action="store_true", help="price of querying part by part")
     args = ap.parse_args()
     if args.lines:
         return lines(args)
+    if args.partition:
+        return partition(args)
     n = int(args.n)
     keys = torch.empty(n, dtype=torch.int64, device="cuda")
     P.gen_u64_keys(keys, 1)
@@ -92,6 +101,62 @@ def lines(args):
         print(f"T={T >> 20:5d} MiB  single {row['single_ms']:.3f} ms  +o^32 {row['pair_xor32_ms']:.3f}  "
               f"+o^64 {row['pair_xor64_ms']:.3f}  +o^128 {row['pair_xor128_ms']:.3f} ms", flush=True)
         del table
+    print(json.dumps(res), flush=True)
+
+
+def partition(args):
+    import torch
+
+    from . import keygen as K
+
+    n = int(args.n)
+    dev = "cuda"
+
+    def t(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.reps
+
+    keys = P.gen_u64_keys(torch.empty(n, dtype=torch.int64, device=dev), K.KEY_SEED)
+    built = P.build_u64_device(keys, index_bits=64, placement="device")
+    del keys
+    mphf = P.Mphf.from_built(built)
+    q = P.gen_query_stream(torch.empty(n, dtype=torch.int64, device=dev), n, K.KEY_SEED, K.ORDER_SEED)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    res = {"n": n}
+    for kpl, block, occ in ((1, 128, 6), (2, 64, 6), (4, 256, 0)):
+        mphf.set_kernel(P.KERNEL_PIPELINED, kpl, block)
+        mphf.set_occupancy(occ)
+        res[f"query_shuffled_ms_{kpl}_{block}_{occ}"] = t(lambda: mphf.query_into(q, out))
+    # the same stream grouped by part: sort it by the slot the MPHF gives
+    # each key (slot = part * S + local), taken from a non-minimal view of
+    # the same pilots
+    pp = built.params.copy()
+    pp.remap_kind, pp.index_bits = P.REMAP_NONE, 64
+    phf = P.Mphf().load(pp, built.pilots, None)
+    order = torch.argsort(phf.query(q))
+    phf.close()
+    qp = q[order]
+    del order
+    for kpl, block, occ in ((1, 128, 6), (2, 64, 6), (4, 256, 0)):
+        mphf.set_kernel(P.KERNEL_PIPELINED, kpl, block)
+        mphf.set_occupancy(occ)
+        res[f"query_by_part_ms_{kpl}_{block}_{occ}"] = t(lambda: mphf.query_into(qp, out))
+    del qp
+    res["copy_16B_per_key_ms"] = min(t(lambda: P.bench_copy(q, out, k, 256)) for k in (1, 2, 4))
+    del q, out
+    torch.cuda.empty_cache()
+    src = torch.empty(1 << 30, dtype=torch.int64, device=dev)
+    src.random_()
+    dst = torch.empty_like(src)
+    res["scatter_2^30_ms"] = t(lambda: P.bench_scatter(src, 30, dst))
+    res["scatter_ns_per_index"] = res["scatter_2^30_ms"] * 1e6 / (1 << 30)
     print(json.dumps(res), flush=True)
 
 

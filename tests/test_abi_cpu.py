@@ -260,3 +260,34 @@ def test_builder_equals_oracle_one_huge_bucket():
     assert b.info.max_bucket_size == n == m.stats.max_bucket_size
     assert b.params.seed == m.params.seed
     assert np.array_equal(b.pilots, m.pilots) and np.array_equal(b.remap, m.clef)
+
+
+def test_probe_arguments_checked_before_any_device_call():
+    """The benchmark probes refuse bad arguments on the host: a scatter whose
+    in and out overlap or whose size is out of range, and a single-launch
+    probe of 2^32 or more work-items (grid times block)."""
+    L = P.lib()
+    a = np.zeros(512, dtype=np.uint64)
+    b = np.zeros(512, dtype=np.uint64)
+    pa, pb = C.c_void_p(a.ctypes.data), C.c_void_p(b.ctypes.data)
+    assert L.ptrhash_bench_scatter(pa, 8, C.c_void_p(a.ctypes.data + 8 * 100), None) == P.E_INVAL
+    assert L.ptrhash_bench_scatter(pa, 7, pb, None) == P.E_INVAL
+    assert L.ptrhash_bench_scatter(pa, 35, pb, None) == P.E_INVAL
+    assert L.ptrhash_bench_scatter(None, 8, pb, None) == P.E_INVAL
+    for kpl, block in [(1, 64), (1, 1024), (2, 256)]:
+        n_q = (2**32 // block + 1) * block * kpl  # one workgroup past 2^32 work-items
+        assert L.ptrhash_bench_copy(pa, n_q, pb, kpl, block, None) == P.E_RANGE
+        assert L.ptrhash_bench_gather(pa, n_q, pa, 256, pb, kpl, block, 0, None) == P.E_RANGE
+
+
+def test_query_entry_points_need_a_loaded_handle_first():
+    """Queries on an empty handle fail with E_STATE whatever the buffers
+    (the overlap and padding checks need the loaded index width)."""
+    h = C.c_void_p()
+    assert P.lib().ptrhash_create(C.byref(h)) == P.OK
+    a = np.zeros(128, dtype=np.uint64)
+    pa = C.c_void_p(a.ctypes.data)
+    assert P.lib().ptrhash_query(h, pa, 10, pa, None) == P.E_STATE
+    assert P.lib().ptrhash_query_bytes(h, pa, 8, pa, 10, pa, None) == P.E_STATE
+    assert P.lib().ptrhash_bench_gather_buckets(h, pa, 10, pa, 1, 256, 0, None) == P.E_STATE
+    assert P.lib().ptrhash_destroy(h) == P.OK

@@ -58,23 +58,27 @@ def _fake_db(path, rows):
     con.close()
 
 
-def test_traffic_scales_by_the_copy_kernel(tmp_path):
-    # copy kernel: 8e9 bytes each way, counted as half the read bytes
-    fetch = tmp_path / "f.db"
+def test_traffic_counts_read_requests_by_size(tmp_path):
+    # two dispatches: 1.0e9 and 1.1e9 128-byte line requests, a few 64- and
+    # 32-byte ones, 8e9 bytes written; DRAM requests reported beside them
+    reads = tmp_path / "r.db"
     write = tmp_path / "w.db"
-    _fake_db(fetch, [("ptrhash::bench_copy_k<1>(...)", "FETCH_SIZE", 4e9 / 1024),
-                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "FETCH_SIZE", 60e9 / 1024),
-                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "FETCH_SIZE", 62e9 / 1024)])
-    _fake_db(write, [("ptrhash::bench_copy_k<1>(...)", "WRITE_SIZE", 8e9 / 1024),
-                     ("ptrhash::query_pipelined<1, unsigned long>(...)", "WRITE_SIZE", 8e9 / 1024)])
+    k = "ptrhash::query_pipelined<1, unsigned long>(...)"
+    _fake_db(reads, [(k, "TCC_EA0_RDREQ_128B_sum", 1.0e9), (k, "TCC_EA0_RDREQ_128B_sum", 1.1e9),
+                     (k, "TCC_EA0_RDREQ_64B_sum", 1e6), (k, "TCC_EA0_RDREQ_64B_sum", 1e6),
+                     (k, "TCC_EA0_RDREQ_32B_sum", 2e6), (k, "TCC_EA0_RDREQ_32B_sum", 2e6),
+                     (k, "TCC_EA0_RDREQ_DRAM_sum", 0.9e9), (k, "TCC_EA0_RDREQ_DRAM_sum", 0.9e9),
+                     ("ptrhash::bench_copy_k<1>(...)", "TCC_EA0_RDREQ_128B_sum", 62.5e6)])
+    _fake_db(write, [("ptrhash::bench_copy_k<1>(...)", "WRITE_SIZE", 8e9 / 1024), (k, "WRITE_SIZE", 8e9 / 1024)])
     out = tmp_path / "t.json"
-    args = type("A", (), {"fetch": str(fetch), "write": str(write), "kernel": "query_pipelined<1, unsigned long>",
-                          "copy": "bench_copy_k<1>", "copy_bytes": 8e9, "scale_from": None, "out": str(out)})
+    args = type("A", (), {"reads": str(reads), "write": str(write), "kernel": "query_pipelined<1, unsigned long>",
+                          "out": str(out)})
     res = profsum.traffic(args)
-    assert res["fetch_scale"] == pytest.approx(2.0)
-    assert res["write_scale"] == pytest.approx(1.0)
-    assert res["fetch_bytes"] == pytest.approx(122e9)  # mean of the two dispatches, doubled
-    assert res["traffic_bytes_per_launch"] == pytest.approx(130e9)
+    assert res["read_bytes"] == pytest.approx(1.05e9 * 128 + 1e6 * 64 + 2e6 * 32)  # mean of the two dispatches
+    assert res["write_bytes"] == pytest.approx(8e9)
+    assert res["traffic_bytes_per_launch"] == pytest.approx(res["read_bytes"] + 8e9)
+    assert res["dram_read_requests"] == pytest.approx(0.9e9)
+    assert "L2" in res["level"]
     assert json.load(open(out))["kernel_source_sha256"] == profsum.kernel_source_hash()
 
 
@@ -86,7 +90,7 @@ def test_profile_lookups_report_only_matching_profiles(tmp_path, monkeypatch):
     assert roof["bound"] == "alu" and roof["achieved"] is None
 
     good = profsum.kernel_source_hash()
-    json.dump({"traffic_bytes_per_launch": 1e9, "fetch_scale": 2.0, "write_scale": 1.0,
+    json.dump({"traffic_bytes_per_launch": 1e9, "read_bytes": 9e8, "write_bytes": 1e8, "level": "L2",
                "kernel_source_sha256": good}, open(tmp_path / "profiles" / "traffic_w.json", "w"))
     b, info = bench.profiled_traffic("w", 10.0, 10**6)
     assert b == 1e9 and info["traffic_GBps"] == pytest.approx(100.0)

@@ -133,8 +133,8 @@ def test_side_by_side_seeds_equal_oracle(n, P_, log2, lam, kseed, stuck_ms, monk
 
 @pytest.mark.parametrize("helpers", ["0", "1", "2", "6", "7"])
 def test_device_search_helper_counts_equal_oracle(helpers, monkeypatch):
-    """Every count of look-ahead wavefronts (the default is 3; 0 runs the
-    leading wavefront alone) gives the oracle's pilots: at the default
+    """Every count of look-ahead wavefronts (the default is 7; 0 runs the
+    placing wavefront alone) gives the oracle's pilots: at the default
     parameters, with Compact's heavy evictions at S = 2^13, and with a
     failing seed."""
     monkeypatch.setenv("PTRHASH_SEARCH_HELPERS", helpers)
@@ -151,6 +151,45 @@ def test_device_search_helper_counts_equal_oracle(helpers, monkeypatch):
         b = P.build_u64_device(dev(keys), params=p, placement="device")
         same(b, m)
         assert b.info.attempts == m.stats.attempts
+
+
+@pytest.mark.parametrize("parts,lam", [(1, 3.5), (2, 3.5), (2, 4.0)])
+def test_device_search_equals_oracle_at_full_part_size(parts, lam):
+    """S = 2^20 slots per part, the part size the parameter rule of Section
+    3.1 ("Parameter values") gives every set beyond about 5*10^7 keys, so the
+    geometry every benchmark MPHF is built with: a 128 KiB taken-slot
+    bitvector that fills the workgroup's LDS. n = floor(0.99 * P * S) keys
+    (alpha = 0.99) and B = ceil(0.99 * S / lambda), Default (lambda = 3.5)
+    and Compact (lambda = 4.0): same seed, pilots, remap bytes and eviction
+    count as the oracle."""
+    log2 = 20
+    n = int(0.99 * parts * (1 << log2))
+    B = int(np.ceil(0.99 * (1 << log2) / lam))
+    keys = K.u64_keys(n, seed=2020 + parts)
+    say(f"[gpu-build] S=2^20 P={parts} lambda={lam} n={n}")
+    m = O.build_u64(keys, params=O.params_explicit(n, parts, log2, B, seed=0))
+    p = lib_params(m, P.REMAP_CLEF, 32)
+    p.seed = 0
+    b = P.build_u64_device(dev(keys), params=p, placement="device")
+    same(b, m)
+    assert b.info.attempts == m.stats.attempts
+    assert b.info.evictions == m.stats.evictions
+    assert b.info.max_part_evictions == m.stats.max_part_evictions
+
+
+def test_device_string_search_equals_oracle_at_full_part_size():
+    """Byte keys at S = 2^20 (two parts, alpha = 0.99, Default lambda)."""
+    log2, parts = 20, 2
+    n = int(0.99 * parts * (1 << log2))
+    B = int(np.ceil(0.99 * (1 << log2) / 3.5))
+    data, off = K.strings(n, seed=2022)
+    say(f"[gpu-build] strings S=2^20 P={parts} n={n}")
+    m = O.build_bytes(data, off, params=O.params_explicit(n, parts, log2, B, seed=0))
+    p = lib_params(m, P.REMAP_CLEF, 32, P.KEY_BYTES)
+    p.seed = 0
+    b = P.build_bytes_device(*dev_strings(data, off), params=p, placement="device")
+    same(b, m)
+    assert b.info.evictions == m.stats.evictions
 
 
 def test_device_search_errors():

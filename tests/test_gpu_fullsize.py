@@ -1,11 +1,14 @@
 """Parity at the full benchmark sizes, in the launch configuration that the
 benchmark times.
 
-At 10^9 u64 keys, 3*10^8 strings and 4.4*10^9 u64 keys the oracle cannot
-build the MPHF inside a test, so the tables come from the library's device
-construction (which the other tests show to be byte-identical to the
-oracle's construction at every size the oracle can build, and to the
-library's host construction at 10^8 keys). The checks here:
+The oracle cannot build the 10^9-key and 3*10^8-string MPHFs inside a test
+(its single-threaded construction takes tens of minutes and about 40 GB),
+so tests/golden/fullsize_digests.json holds the SHA-256 of the pilot array
+and of the CacheLineEF bytes that the oracle built for exactly these key
+sets, written once by tests/golden/make_fullsize_digests.py (which calls
+only the oracle and the seeded generators). The device construction here
+must reproduce both digests, its seed and its eviction count, so the tables
+the GPU queries are the oracle's own. Then:
 
 * parameters equal the oracle's parameter rule;
 * the kernel choice is the one the benchmark's autotuner picks, over the same
@@ -13,19 +16,27 @@ library's host construction at 10^8 keys). The checks here:
   every output;
 * all members map bijectively onto [0, n) (a property that holds at any
   size);
-* the oracle's query formula, evaluated one key at a time on sampled
-  positions of the stream (the first and last 2^18 and 2^20 random ones),
-  gives exactly the GPU's indices. The sampled keys are regenerated on the
-  host from the seeded generators, not read back from the device;
+* every index of the whole query stream equals the oracle's query of the
+  same key, the oracle's loop split over the host's threads; the keys of
+  sampled positions (the first and last 2^18 and 2^20 random ones) are also
+  regenerated on the host from the seeded generators and must equal the
+  device-generated stream;
 * non-members: 2^20 of them, every output equal to the oracle's.
+
+4.4*10^9 keys are beyond the oracle's memory here: there the device build
+is checked by bijection and sampled oracle parity only.
 
 The 64-MPHF workload runs at its full size too: 4096 requests (24.1 M keys)
 in one multi-MPHF launch with the autotuner's shape, and 2000 of them
 through the server, every index equal to the oracle's query of the
 request's own MPHF.
 """
+import hashlib
+import json
+import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -81,6 +92,60 @@ def to_u64(t):
     return a.view(np.uint64) if a.dtype == np.int64 else a.view(np.uint32).astype(np.uint64)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_digests.json")
+
+
+def host_threads():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def check_golden(name, built):
+    """The device build equals the oracle's build of the same set: seed,
+    eviction count and SHA-256 of the pilots and of the CacheLineEF bytes."""
+    if not os.path.exists(GOLDEN) or name not in json.load(open(GOLDEN)):
+        pytest.fail(f"no oracle digest for {name} in {GOLDEN}")
+    g = json.load(open(GOLDEN))[name]
+    p = built.params
+    assert (p.n, p.num_parts, p.log2_slots, p.buckets_per_part) == (g["n"], g["num_parts"], g["log2_slots"],
+                                                                    g["buckets_per_part"])
+    assert p.seed == g["seed"] and built.info.attempts == g["attempts"]
+    assert built.info.evictions == g["evictions"]
+    assert hashlib.sha256(memoryview(built.pilots)).hexdigest() == g["pilots_sha256"]
+    assert hashlib.sha256(memoryview(built.remap)).hexdigest() == g["clef_sha256"]
+    say(f"[fullsize] {name}: device build == oracle build (digests, seed {p.seed}, {g['evictions']} evictions)")
+
+
+def oracle_whole_u64(m, keys):
+    """The oracle's query of every key, in slices over the host's threads."""
+    bounds = np.linspace(0, len(keys), host_threads() * 4 + 1).astype(np.int64)
+    out = np.empty(len(keys), dtype=np.uint64)
+
+    def run(i):
+        lo, hi = int(bounds[i]), int(bounds[i + 1])
+        if hi > lo:
+            out[lo:hi] = O.query_u64(m, keys[lo:hi], O.REMAP_CLEF)
+
+    with ThreadPoolExecutor(host_threads()) as ex:
+        list(ex.map(run, range(len(bounds) - 1)))
+    return out
+
+
+def oracle_whole_bytes(m, data, offs):
+    n = len(offs) - 1
+    bounds = np.linspace(0, n, host_threads() * 4 + 1).astype(np.int64)
+    out = np.empty(n, dtype=np.uint64)
+
+    def run(i):
+        lo, hi = int(bounds[i]), int(bounds[i + 1])
+        if hi > lo:
+            o = offs[lo:hi + 1]
+            out[lo:hi] = O.query_bytes(m, data[int(o[0]):int(o[-1]) + 64], o - o[0], O.REMAP_CLEF)
+
+    with ThreadPoolExecutor(host_threads()) as ex:
+        list(ex.map(run, range(len(bounds) - 1)))
+    return out
+
+
 def tuned(mphf, run, n_q, key_kind):
     best, _ = autotune.tune(torch, mphf, run, n_q, cands=autotune.candidates_for(key_kind), use_cache=False)
     say(f"[fullsize] tuned choice {best}")
@@ -95,6 +160,7 @@ def test_u64_1e9_default():
     del keys
     torch.cuda.empty_cache()
     check_params(built.params, n)
+    check_golden("u64_1e9", built)
     mphf = P.Mphf.from_built(built)
     q = P.gen_query_stream(torch.empty(n, dtype=torch.int64, device=DEV), n, K.KEY_SEED, K.ORDER_SEED)
     out = torch.empty(n, dtype=torch.int64, device=DEV)
@@ -104,13 +170,20 @@ def test_u64_1e9_default():
     say("[fullsize] u64 bijection")
     assert bijective(out, n)
 
-    say("[fullsize] u64 sampled oracle parity")
+    say("[fullsize] u64 stream keys at sampled positions regenerated on the host")
     pos = sample_positions(n, 11)
     qs = K.query_stream_at(n, pos)
     assert np.array_equal(to_u64(q[torch.from_numpy(pos.astype(np.int64)).to(DEV)]), qs)
-    ref = O.query_u64(oracle_of(built), qs, O.REMAP_CLEF)
-    got = to_u64(out[torch.from_numpy(pos.astype(np.int64)).to(DEV)])
-    assert np.array_equal(got, ref)
+
+    say(f"[fullsize] u64 whole-stream oracle parity ({n} keys, {host_threads()} host threads)")
+    t0 = time.time()
+    qh = to_u64(q)
+    ref = oracle_whole_u64(oracle_of(built), qh)
+    got = to_u64(out)
+    bad = int(np.count_nonzero(got != ref))
+    say(f"[fullsize] oracle over the whole stream in {time.time() - t0:.1f} s: {bad} differences")
+    assert bad == 0
+    del qh, ref, got
 
     say("[fullsize] u64 non-members, tuned and plain kernels")
     nm = K.nonmember_keys(RANDOM, seed=31)
@@ -133,21 +206,33 @@ def test_bytes_3e8_default():
     del d_data, d_off
     torch.cuda.empty_cache()
     check_params(built.params, n)
+    check_golden("bytes_3e8", built)
     mphf = P.Mphf.from_built(built)
     qd, qo = P.gen_strings(n, K.KEY_SEED, K.ORDER_SEED, shuffled=True)
     out = torch.empty(n, dtype=torch.int32, device=DEV)
-    tuned(mphf, lambda: mphf.query_bytes_into(qd, qo, out), n, P.KEY_BYTES)
+    tuned(mphf, lambda: mphf.query_bytes_into(qd, qo, out, check_end=False), n, P.KEY_BYTES)
     mphf.query_bytes_into(qd, qo, out)
     torch.cuda.synchronize()
     say("[fullsize] strings bijection")
     assert bijective(out, n)
 
-    say("[fullsize] strings sampled oracle parity")
+    say("[fullsize] strings at sampled positions regenerated on the host")
     pos = sample_positions(n, 12)
     sd, so = K.string_query_stream_at(n, pos)
     ref = O.query_bytes(oracle_of(built), sd, so, O.REMAP_CLEF)
     got = to_u64(out[torch.from_numpy(pos.astype(np.int64)).to(DEV)])
     assert np.array_equal(got, ref)
+
+    say(f"[fullsize] strings whole-stream oracle parity ({n} strings, {host_threads()} host threads)")
+    t0 = time.time()
+    hd = qd.cpu().numpy()
+    ho = qo.cpu().numpy().view(np.uint64)
+    ref = oracle_whole_bytes(oracle_of(built), hd, ho)
+    got = to_u64(out)
+    bad = int(np.count_nonzero(got != ref))
+    say(f"[fullsize] oracle over the whole stream in {time.time() - t0:.1f} s: {bad} differences")
+    assert bad == 0
+    del hd, ho, ref, got
 
     say("[fullsize] strings: plain kernel agrees")
     mphf.set_kernel(P.KERNEL_PLAIN, 1, 256)
@@ -195,6 +280,42 @@ def test_u64_beyond_2_32_keys():
     ref = O.query_u64(oracle_of(built), qs, O.REMAP_CLEF)
     assert np.array_equal(got, ref)
     assert int(ref.max()) >= 2**32  # the sample reaches indices beyond 32 bits
+
+
+def test_launch_split_beyond_2_31_work_items():
+    """2,147,500,000 queries (more than 2^31 work-items with one key per lane
+    and 64-thread workgroups) against a 10^5-key MPHF: the library splits the
+    batch into launches of at most 2^31 work-items. The stream is the shuffled
+    member stream repeated, so every period's indices must equal the first's,
+    which equal the oracle's, and the keys around the split equal it too."""
+    n, reps = 100_000, 21_475
+    n_q = n * reps
+    assert n_q > 2**31
+    keys = K.u64_keys(n, seed=8)
+    m = O.build_u64(keys)
+    period = K.query_stream(n, key_seed=8)
+    want = O.query_u64(m, period, O.REMAP_CLEF)
+    g = P.Mphf().load(*_lib_load_args(m))
+    q = torch.from_numpy(period.view(np.int64)).to(DEV).repeat(reps)
+    out = torch.empty(n_q, dtype=torch.int32, device=DEV)
+    for kern, kpl, blk in [(P.KERNEL_PLAIN, 1, 64), (P.KERNEL_PIPELINED, 1, 64)]:
+        say(f"[fullsize] {n_q} queries, kernel {kern} keys/lane {kpl} block {blk}")
+        g.set_kernel(kern, kpl, blk)
+        out.fill_(-1)
+        g.query_into(q, out)
+        torch.cuda.synchronize()
+        head = out[:n]
+        assert np.array_equal(to_u64(head), want)
+        assert bool((out.view(reps, n) == head).all())
+        split = 2**31
+        assert np.array_equal(to_u64(out[split - 8:split + 8]), want[(np.arange(split - 8, split + 8)) % n])
+    del q, out
+
+
+def _lib_load_args(m):
+    from .mphf_pairs import lib_params
+
+    return lib_params(m, P.REMAP_CLEF, 32), m.pilots, m.clef
 
 
 def oracle_of_params(b):

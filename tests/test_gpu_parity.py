@@ -154,9 +154,97 @@ def test_empty_query_and_errors():
     out = torch.empty(0, dtype=torch.int32, device=DEV)
     g.query_into(empty, out)  # no launch
     with pytest.raises(P.PtrHashError) as e:
-        g.query_bytes(torch.zeros(8, dtype=torch.uint8, device=DEV), torch.zeros(2, dtype=torch.int64, device=DEV))
+        g.query_bytes(torch.zeros(64, dtype=torch.uint8, device=DEV), torch.zeros(2, dtype=torch.int64, device=DEV))
     assert e.value.code == P.E_STATE
     torch.cuda.synchronize()
+
+
+def test_overlapping_buffers_are_refused():
+    """keys/out (u64), data/offsets/out (bytes) and the batches of one
+    multi-MPHF launch must not overlap: E_INVAL before any launch, while
+    buffers that only touch are taken."""
+    keys, m = oracle_mphf(1000)
+    g = load(m, P.REMAP_CLEF, 32)
+    want = O.query_u64(m, keys)
+    buf = torch.zeros(4096, dtype=torch.int64, device=DEV)
+    buf[:1000] = torch.from_numpy(keys.view(np.int64)).to(DEV)
+    k = buf[:1000]
+    for lo, hi in [(0, 500), (500, 1000), (999, 1499)]:  # int32 out overlapping the keys' bytes
+        with pytest.raises(P.PtrHashError) as e:
+            g.query_into(k, buf[lo:hi].view(torch.int32))
+        assert e.value.code == P.E_INVAL
+    out = buf[1000:1500].view(torch.int32)  # starts where the keys end
+    g.query_into(k, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32).astype(np.uint64), want)
+
+    data, off = K.strings(100, seed=5)
+    mb = O.build_bytes(data, off)
+    gb = load(mb, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES)
+    d = torch.from_numpy(data).to(DEV)
+    o = torch.from_numpy(off.view(np.int64)).to(DEV)
+    with pytest.raises(P.PtrHashError) as e:
+        gb.query_bytes_into(d, o, d[:400].view(torch.int32))
+    assert e.value.code == P.E_INVAL
+    with pytest.raises(P.PtrHashError) as e:
+        gb.query_bytes_into(d, o, o[:50].view(torch.int32))
+    assert e.value.code == P.E_INVAL
+
+    k2 = buf[2000:3000]
+    k2.copy_(k)
+    o1 = torch.empty(1000, dtype=torch.int32, device=DEV)
+    with pytest.raises(P.PtrHashError) as e:  # two batches writing the same indices
+        P.query_multi([(g, k, o1), (g, k2, o1)])
+    assert e.value.code == P.E_INVAL
+    with pytest.raises(P.PtrHashError) as e:  # one batch's out inside another batch's keys
+        P.query_multi([(g, k, o1), (g, k2, k[:500].view(torch.int32))])
+    assert e.value.code == P.E_INVAL
+    o2 = torch.empty(1000, dtype=torch.int32, device=DEV)
+    P.query_multi([(g, k, o1), (g, k2, o2)])  # two batches reading the same keys is fine
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    assert np.array_equal(o1.cpu().numpy().view(np.uint32).astype(np.uint64), want)
+
+
+def test_bad_string_offsets_are_not_read():
+    """The offsets live on the device, so the kernel checks them: a key whose
+    end precedes its start, or ends past data_len - 16, is not read and gets
+    an index of all ones; every other key keeps its index. The binding
+    refuses a data tensor shorter than the last offset plus 64 bytes."""
+    n = 1000
+    data, off = K.strings(n, seed=3)
+    m = O.build_bytes(data, off)
+    want = O.query_bytes(m, data, off)
+    g = load(m, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES)
+    d = torch.from_numpy(data).to(DEV)
+    bad_off = off.copy()
+    bad_off[11] = bad_off[10] - 1  # key 10 ends before it starts; key 11 then starts after... its own start
+    bad_off[n] = len(data) + 4096  # the last key ends far past the buffer
+    o = torch.from_numpy(bad_off.view(np.int64)).to(DEV)
+    with pytest.raises(ValueError):
+        g.query_bytes(d, o)
+    for kern, kpl, blk in [(P.KERNEL_PLAIN, 1, 256), (P.KERNEL_PIPELINED, 4, 256)]:
+        say(f"[parity-bytes] bad offsets kernel={kern} kpl={kpl}")
+        g.set_kernel(kern, kpl, blk)
+        out = torch.empty(n, dtype=torch.int32, device=DEV)
+        g.query_bytes_into(d, o, out, check_end=False)
+        got = out.cpu().numpy().view(np.uint32).astype(np.uint64)
+        assert got[10] == 0xFFFFFFFF and got[n - 1] == 0xFFFFFFFF
+        keep = np.ones(n, dtype=bool)
+        keep[[10, 11, n - 1]] = False  # key 11 now spans [off[10] - 1, off[12]): another string
+        assert np.array_equal(got[keep], want[keep])
+        want11 = O.query_bytes(m, data, np.array([bad_off[11], off[12]], dtype=np.uint64))
+        assert got[11] == want11[0]
+    # the same keys in a multi-MPHF batch, with a data_len below the padding refused
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    P.query_multi([(g, (d, o), out)])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert got[10] == 0xFFFFFFFF and got[n - 1] == 0xFFFFFFFF
+    assert np.array_equal(got[keep], want[keep])
+    with pytest.raises(P.PtrHashError) as e:
+        P.query_multi([(g, (d[:32], o), out)])
+    assert e.value.code == P.E_INVAL
 
 
 def test_device_generators_match_host():

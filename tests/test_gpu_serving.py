@@ -162,3 +162,34 @@ def test_mapped_requests_in_place(zero_copy):
     assert e.value.code == P.E_INVAL
     srv.close()
     buf.close()
+
+
+@pytest.mark.parametrize("zero_copy", [1, 0])
+def test_loaded_replay_overlaps_launches(zero_copy):
+    """A saturating Poisson replay (mean gap 2 us, sizes log-uniform up to
+    65536 keys) over four launch slots: several slots are busy at once, the
+    launches overlap on the device (each launch's start and done events on
+    its stream), and every request's indices equal its result alone."""
+    rng = np.random.default_rng(12)
+    reqs = requests(rng, 600, 65_536)
+    srv = P.Server(streams=4, max_batches=16, slot_keys=1 << 17, max_queued_keys=1 << 30, zero_copy=zero_copy)
+    say(f"[serve] overlap: {len(reqs)} requests alone, zero_copy={zero_copy}")
+    alone = []
+    for g, q, out, want in reqs:
+        srv.wait(srv.submit(g, q, out))
+        assert np.array_equal(out.astype(np.uint64), want)
+        alone.append(out.copy())
+        out[:] = 0
+    srv.reset_stats()
+    arrivals = np.cumsum(rng.exponential(2.0, size=len(reqs)))
+    say("[serve] overlap: loaded replay")
+    srv.replay([(g, q, out, t) for (g, q, out, _), t in zip(reqs, arrivals)])
+    st = srv.stats()
+    say(f"[serve] overlap: launches {st['launches']} slots busy at most {st['slots_busy_max']}, on the device at "
+        f"most {st['overlap_max']} at once, {st['overlap_mean']:.2f} on average")
+    for (_, _, out, _), a in zip(reqs, alone):
+        assert np.array_equal(out, a)
+    assert st["completed"] == len(reqs)
+    assert st["slots_busy_max"] >= 2
+    assert st["overlap_max"] >= 2 and st["overlap_mean"] > 1.0
+    srv.close()
