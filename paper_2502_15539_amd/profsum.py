@@ -11,6 +11,10 @@
         (TCC_EA0_RDREQ_DRAM_sum) beside them, since reads served by the MALL
         do not reach HBM. The JSON records a hash of the kernel sources so
         that a later change voids it.
+    python -m paper_2502_15539_amd.profsum overlap DB --kernel SUBSTR
+        from a kernel trace: dispatches of the kernel, the most running at
+        one instant, the time-weighted mean number running while any runs,
+        and the share of their busy time with two or more running
     python -m paper_2502_15539_amd.profsum valu --db DB --kernel SUBSTR --out JSON
         vector-ALU instructions per launch of a kernel (SQ_INSTS_VALU, counted
         per wavefront) with the VALUBusy and VALUUtilization metrics, and the
@@ -91,18 +95,49 @@ def traffic(args) -> dict:
     if not sized:
         raise SystemExit(f"no TCC_EA0_RDREQ_<size>B_sum counters for {args.kernel!r} in {args.reads}")
     read_bytes = sum(size * v for size, v in sized.items())
+    dram32 = dict(reads).get("TCC_EA0_RDREQ_DRAM_32B_sum")
     k_write = _mean(args.write, args.kernel, "WRITE_SIZE") * 1024.0
     other = {c: v for c, v in reads if not re.fullmatch(r"TCC_EA0_RDREQ_(\d+)B_sum", c)}
+    other.pop("TCC_EA0_RDREQ_DRAM_32B_sum", None)
     res = {"kernel": args.kernel,
            "level": "L2 to memory fabric: read requests by size plus WRITE_SIZE (includes MALL hits)",
            "read_requests_by_size": {f"{k}B": v for k, v in sorted(sized.items())},
            "read_bytes": read_bytes, "write_bytes": k_write,
            "dram_read_requests": other.get("TCC_EA0_RDREQ_DRAM_sum"),
+           "dram_read_bytes": None if dram32 is None else 32.0 * dram32,
            "read_requests": other.get("TCC_EA0_RDREQ_sum"),
            "traffic_bytes_per_launch": read_bytes + k_write, "kernel_source_sha256": kernel_source_hash()}
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     return res
+
+
+def dispatch_spans(db: str, kernel_sub: str):
+    """(start, end) of every dispatch of a kernel in a rocpd kernel trace."""
+    cur = sqlite3.connect(db).cursor()
+    cur.execute("select * from kernels limit 1")
+    cols = [d[0] for d in cur.description]
+    name = next(c for c in ("name", "kernel_name") if c in cols)
+    start = next(c for c in ("start", "start_ns", "begin") if c in cols)
+    end = next(c for c in ("end", "end_ns", "stop") if c in cols)
+    rows = cur.execute(f'select "{name}", "{start}", "{end}" from kernels').fetchall()
+    return [(float(b), float(e)) for n, b, e in rows if kernel_sub in n]
+
+
+def overlap_stats(spans) -> dict:
+    ev = sorted([(b, 1) for b, _ in spans] + [(e, -1) for _, e in spans])  # an end sorts first at a tie
+    open_, top, prev, busy, multi = 0, 0, 0.0, 0.0, 0.0
+    for t, d in ev:
+        if open_ > 0:
+            busy += t - prev
+            if open_ > 1:
+                multi += t - prev
+        open_ += d
+        top = max(top, open_)
+        prev = t
+    total = sum(e - b for b, e in spans)
+    return {"dispatches": len(spans), "max_concurrent": top, "mean_concurrent": total / busy if busy else 0.0,
+            "share_of_busy_time_with_2_or_more": multi / busy if busy else 0.0}
 
 
 def valu(args) -> dict:
@@ -127,6 +162,9 @@ def main():
     r.add_argument("--write", required=True, help="DB with WRITE_SIZE")
     r.add_argument("--kernel", required=True)
     r.add_argument("--out", required=True)
+    o = sub.add_parser("overlap")
+    o.add_argument("db")
+    o.add_argument("--kernel", required=True)
     v = sub.add_parser("valu")
     v.add_argument("--db", required=True)
     v.add_argument("--kernel", required=True)
@@ -136,6 +174,8 @@ def main():
         print(trace(a.db))
     elif a.cmd == "counters":
         print(counters(a.dbs))
+    elif a.cmd == "overlap":
+        print(json.dumps(overlap_stats(dispatch_spans(a.db, a.kernel)), indent=1))
     elif a.cmd == "valu":
         print(json.dumps(valu(a), indent=1))
     else:

@@ -80,7 +80,9 @@ def run_server(srv, reqs, arrivals, mapped=False):
     keys = sum(len(q) for _, q, _ in reqs)
     return {"requests": len(reqs), "keys": keys, "makespan_s": span, "req_per_s": len(reqs) / span,
             "keys_per_s": keys / span, "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-            "wait_p50_us": st["wait_p50_us"], "wait_p99_us": st["wait_p99_us"], "launches": st["launches"]}
+            "wait_p50_us": st["wait_p50_us"], "wait_p99_us": st["wait_p99_us"], "launches": st["launches"],
+            "slots_busy_max": st["slots_busy_max"], "device_overlap_max": st["overlap_max"],
+            "device_overlap_mean": st["overlap_mean"]}
 
 
 def run_plain_baseline(reqs, torch):
@@ -213,7 +215,9 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
         r["offered_req_per_s"] = rate
         runs.append(r)
         log(f"[serve] load {f:.2f}: {r['req_per_s']:.0f} req/s p50 {r['p50_us']:.0f}us p99 {r['p99_us']:.0f}us "
-            f"(wait p50 {r['wait_p50_us']:.0f}us p99 {r['wait_p99_us']:.0f}us) launches={r['launches']}")
+            f"(wait p50 {r['wait_p50_us']:.0f}us p99 {r['wait_p99_us']:.0f}us) launches={r['launches']} "
+            f"slots busy <= {r['slots_busy_max']}, on the device <= {r['device_overlap_max']} at once "
+            f"({r['device_overlap_mean']:.2f} on average)")
     srv.close()
     served = [o.copy() for _, _, o in rq]
     buf.close()

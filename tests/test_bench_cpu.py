@@ -138,3 +138,20 @@ def test_binding_refuses_buffers_a_kernel_would_overrun():
                    (_FakeDeviceTensor(9, 8), "10 are needed")]:
         with pytest.raises(ValueError, match=msg):
             P._device_tensor(t, "keys", 8, 10)
+
+
+def test_overlap_of_dispatches(tmp_path):
+    db = tmp_path / "k.db"
+    con = sqlite3.connect(db)
+    con.execute('create table kernels (name text, start integer, "end" integer)')
+    k = "ptrhash::query_multi<4>(...)"
+    con.executemany("insert into kernels values (?, ?, ?)",
+                    [(k, 0, 10), (k, 5, 15), (k, 15, 20), ("other", 0, 100), (k, 30, 40)])
+    con.commit()
+    con.close()
+    spans = profsum.dispatch_spans(str(db), "query_multi")
+    assert sorted(spans) == [(0, 10), (5, 15), (15, 20), (30, 40)]
+    st = profsum.overlap_stats(spans)
+    assert st["dispatches"] == 4 and st["max_concurrent"] == 2  # 15 ends as 15 starts: no third
+    assert st["mean_concurrent"] == pytest.approx(35 / 30)
+    assert st["share_of_busy_time_with_2_or_more"] == pytest.approx(5 / 30)
