@@ -233,6 +233,22 @@ PTRHASH_API int ptrhash_set_multi_kernel(int keys_per_lane, int block, int block
 PTRHASH_API int ptrhash_query_multi(const ptrhash_query_desc *descs, int k, hipStream_t stream);
 PTRHASH_API int ptrhash_multi_max(void);
 
+/*
+ * For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid hipMalloc): as ptrhash_query_multi, with results identical to it,
+ * but nothing is allocated on the device or the host. The batch table goes
+ * into a fixed device array of the library (about 35 KB on each GPU it runs
+ * on, held until the process ends) through a fixed host array, copied on
+ * stream ahead of the launch (a copy from pageable memory, which returns
+ * once the table has left the host array). At most 256 batches per call
+ * (E_RANGE beyond). Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU, on different streams or from different threads,
+ * race; calls one after the other on one stream do not. Not for use while
+ * the stream is being captured (E_STATE). Other errors as
+ * ptrhash_query_multi.
+ */
+PTRHASH_API int ptrhash_query_multi_noalloc(const ptrhash_query_desc *descs, int k, hipStream_t stream);
+
 /* ---- Serving: continuous batching over resident MPHFs (row A8) ---- */
 
 /* streams: launch slots in flight at once (1..16; a process gets

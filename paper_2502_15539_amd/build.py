@@ -15,7 +15,7 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PTRHASH_ARCH", "gfx950")
 
 HIP_SOURCES = ["api.hip", "kernels.hip", "roofline.hip", "keygen.hip", "server.hip", "build_device.hip",
-               "place_device.hip"]
+               "place_device.hip", "noalloc.hip"]
 CXX_SOURCES = ["builder.cpp"]
 
 # Packed FP32 instructions are kept out of every HIP object on purpose.

@@ -77,10 +77,10 @@ __host__ __device__ inline const DevMphf *multi_mphfs(const MultiTable *t) {
 
 // Bytes of a table of `count` batches over `mphfs` distinct MPHFs, and the
 // most a table of up to max_batches batches can take.
-inline size_t multi_table_bytes(uint32_t count, uint32_t mphfs) {
+constexpr size_t multi_table_bytes(uint32_t count, uint32_t mphfs) {
     return sizeof(MultiTable) + (size_t)count * (sizeof(uint64_t) + sizeof(MultiBatch)) + (size_t)mphfs * sizeof(DevMphf);
 }
-inline size_t multi_table_capacity(int max_batches) {
+constexpr size_t multi_table_capacity(int max_batches) {
     const uint32_t m = max_batches > 0 ? (uint32_t)max_batches : 0;
     return multi_table_bytes(m, m);
 }

@@ -149,6 +149,7 @@ _SIGS = {
     "ptrhash_multi_plan_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ptrhash_query_multi": (C.c_int, [C.POINTER(QueryDesc), C.c_int, C.c_void_p]),
     "ptrhash_multi_max": (C.c_int, []),
+    "ptrhash_query_multi_noalloc": (C.c_int, [C.POINTER(QueryDesc), C.c_int, C.c_void_p]),
     "ptrhash_server_default_config": (C.c_int, [C.POINTER(ServerConfig)]),
     "ptrhash_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
     "ptrhash_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
@@ -519,6 +520,13 @@ def query_multi(batches, stream=None):
     """One persistent launch over all batches (see ptrhash_query_multi)."""
     arr = make_descs(batches)
     _check(lib().ptrhash_query_multi(arr, len(batches), _stream(stream)), "ptrhash_query_multi")
+
+
+def query_multi_noalloc(batches, stream=None):
+    """As query_multi through the entry point that allocates nothing (a fixed
+    table of at most 256 batches per GPU; see ptrhash_query_multi_noalloc)."""
+    arr = make_descs(batches)
+    _check(lib().ptrhash_query_multi_noalloc(arr, len(batches), _stream(stream)), "ptrhash_query_multi_noalloc")
 
 
 class HostBuffer:
