@@ -15,6 +15,11 @@
         from a kernel trace: dispatches of the kernel, the most running at
         one instant, the time-weighted mean number running while any runs,
         and the share of their busy time with two or more running
+    python -m paper_2502_15539_amd.profsum steps DB --kernel NAME --before SUBSTR --count N
+        durations of the timed launches in a kernel trace of bench.py: the
+        last N dispatches of the kernel named NAME (exactly) that start
+        before the first dispatch whose name contains SUBSTR (the benchmark
+        times its query steps right before its roofline kernels)
     python -m paper_2502_15539_amd.profsum valu --db DB --kernel SUBSTR --out JSON
         vector-ALU instructions per launch of a kernel (SQ_INSTS_VALU, counted
         per wavefront) with the VALUBusy and VALUUtilization metrics, and the
@@ -112,8 +117,8 @@ def traffic(args) -> dict:
     return res
 
 
-def dispatch_spans(db: str, kernel_sub: str):
-    """(start, end) of every dispatch of a kernel in a rocpd kernel trace."""
+def dispatches(db: str):
+    """(name, start, end) of every dispatch in a rocpd kernel trace, by start."""
     cur = sqlite3.connect(db).cursor()
     cur.execute("select * from kernels limit 1")
     cols = [d[0] for d in cur.description]
@@ -121,7 +126,25 @@ def dispatch_spans(db: str, kernel_sub: str):
     start = next(c for c in ("start", "start_ns", "begin") if c in cols)
     end = next(c for c in ("end", "end_ns", "stop") if c in cols)
     rows = cur.execute(f'select "{name}", "{start}", "{end}" from kernels').fetchall()
-    return [(float(b), float(e)) for n, b, e in rows if kernel_sub in n]
+    return sorted(((n, float(b), float(e)) for n, b, e in rows), key=lambda r: r[1])
+
+
+def dispatch_spans(db: str, kernel_sub: str):
+    """(start, end) of every dispatch of a kernel in a rocpd kernel trace."""
+    return [(b, e) for n, b, e in dispatches(db) if kernel_sub in n]
+
+
+def timed_steps(rows, kernel: str, before: str, count: int) -> dict:
+    """The last `count` dispatches of the kernel whose short name is `kernel`
+    that start before the first dispatch whose name contains `before`
+    (times in ns, durations reported in ms)."""
+    stop = next((b for n, b, _ in rows if before in n), float("inf"))
+    mine = [(b, e) for n, b, e in rows if short(n) == kernel and b < stop][-count:]
+    if len(mine) < count:
+        raise SystemExit(f"only {len(mine)} dispatches of {kernel} before {before}")
+    d = [(e - b) / 1e6 for b, e in mine]
+    return {"kernel": kernel, "dispatches": len(d), "avg_ms": sum(d) / len(d), "min_ms": min(d), "max_ms": max(d),
+            "first_to_last_ms_per_step": (mine[-1][1] - mine[0][0]) / 1e6 / len(d)}
 
 
 def overlap_stats(spans) -> dict:
@@ -162,6 +185,11 @@ def main():
     r.add_argument("--write", required=True, help="DB with WRITE_SIZE")
     r.add_argument("--kernel", required=True)
     r.add_argument("--out", required=True)
+    st = sub.add_parser("steps")
+    st.add_argument("db")
+    st.add_argument("--kernel", required=True)
+    st.add_argument("--before", required=True)
+    st.add_argument("--count", type=int, default=20)
     o = sub.add_parser("overlap")
     o.add_argument("db")
     o.add_argument("--kernel", required=True)
@@ -174,6 +202,8 @@ def main():
         print(trace(a.db))
     elif a.cmd == "counters":
         print(counters(a.dbs))
+    elif a.cmd == "steps":
+        print(json.dumps(timed_steps(dispatches(a.db), a.kernel, a.before, a.count), indent=1))
     elif a.cmd == "overlap":
         print(json.dumps(overlap_stats(dispatch_spans(a.db, a.kernel)), indent=1))
     elif a.cmd == "valu":

@@ -155,3 +155,14 @@ def test_overlap_of_dispatches(tmp_path):
     assert st["dispatches"] == 4 and st["max_concurrent"] == 2  # 15 ends as 15 starts: no third
     assert st["mean_concurrent"] == pytest.approx(35 / 30)
     assert st["share_of_busy_time_with_2_or_more"] == pytest.approx(5 / 30)
+
+
+def test_timed_steps_are_the_last_before_the_rooflines():
+    q = "void ptrhash::query_pipelined<1, unsigned long>(unsigned long const*, ...)"
+    rows = [(q, 0, 30e6), (q, 40e6, 60e6)] + [(q, 100e6 + i * 20e6, 100e6 + i * 20e6 + 18e6) for i in range(5)]
+    rows += [("void ptrhash::bench_gather_k<2>(...)", 300e6, 320e6), (q, 400e6, 450e6)]
+    st = profsum.timed_steps(rows, "ptrhash::query_pipelined<1, unsigned long>", "bench_gather", 3)
+    assert st["dispatches"] == 3 and st["avg_ms"] == pytest.approx(18.0)
+    assert st["first_to_last_ms_per_step"] == pytest.approx((198e6 - 140e6) / 1e6 / 3)
+    with pytest.raises(SystemExit):
+        profsum.timed_steps(rows, "ptrhash::query_pipelined<1, unsigned long>", "bench_gather", 9)
