@@ -191,7 +191,7 @@ def profiled_traffic(workload, ms, n):
     info = {"level": t.get("level", ""), "traffic_GBps": b / (ms / 1e3) / 1e9,
             "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic_bytes_per_key": b / n,
             "read_bytes": t.get("read_bytes"), "write_bytes": t.get("write_bytes"),
-            "dram_read_requests": t.get("dram_read_requests"), "source": os.path.relpath(path, ROOT)}
+            "memory_read_bytes": t.get("memory_read_bytes"), "source": os.path.relpath(path, ROOT)}
     return b, info
 
 

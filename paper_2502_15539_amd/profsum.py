@@ -7,10 +7,11 @@
     python -m paper_2502_15539_amd.profsum traffic --reads DB --write DB --kernel SUBSTR --out JSON
         Bytes per launch of a kernel between the L2 caches and the memory
         fabric: read requests counted by size (TCC_EA0_RDREQ_<size>B_sum,
-        each times its size) plus WRITE_SIZE; DRAM read requests
-        (TCC_EA0_RDREQ_DRAM_sum) beside them, since reads served by the MALL
-        do not reach HBM. The JSON records a hash of the kernel sources so
-        that a later change voids it.
+        each times its size) plus WRITE_SIZE; beside them the read bytes
+        addressed to memory rather than to other agents
+        (TCC_EA0_RDREQ_DRAM_32B_sum, in 32-byte units), which still include
+        what the MALL on the memory side serves. The JSON records a hash of
+        the kernel sources so that a later change voids it.
     python -m paper_2502_15539_amd.profsum overlap DB --kernel SUBSTR
         from a kernel trace: dispatches of the kernel, the most running at
         one instant, the time-weighted mean number running while any runs,
@@ -104,12 +105,12 @@ def traffic(args) -> dict:
     k_write = _mean(args.write, args.kernel, "WRITE_SIZE") * 1024.0
     other = {c: v for c, v in reads if not re.fullmatch(r"TCC_EA0_RDREQ_(\d+)B_sum", c)}
     other.pop("TCC_EA0_RDREQ_DRAM_32B_sum", None)
+    other.pop("TCC_EA0_RDREQ_DRAM_sum", None)
     res = {"kernel": args.kernel,
            "level": "L2 to memory fabric: read requests by size plus WRITE_SIZE (includes MALL hits)",
            "read_requests_by_size": {f"{k}B": v for k, v in sorted(sized.items())},
            "read_bytes": read_bytes, "write_bytes": k_write,
-           "dram_read_requests": other.get("TCC_EA0_RDREQ_DRAM_sum"),
-           "dram_read_bytes": None if dram32 is None else 32.0 * dram32,
+           "memory_read_bytes": None if dram32 is None else 32.0 * dram32,
            "read_requests": other.get("TCC_EA0_RDREQ_sum"),
            "traffic_bytes_per_launch": read_bytes + k_write, "kernel_source_sha256": kernel_source_hash()}
     with open(args.out, "w") as f:

@@ -13,6 +13,13 @@ second byte read at o xor D of every random offset o (D = 32, 64, 128): a
 second byte in the same 128-byte line costs nothing if a miss fills the
 whole line, and a second miss if it does not.
 
+--memtypes times the pure gather (2^28 random bytes) from a table of the
+10^9-key pilot array's size in default, fine-grained and uncached device
+memory (hipExtMallocWithFlags); run it under rocprofv3 --pmc with the
+TCC_EA0_RDREQ_<size>B counters to see the request size. The tables are not
+freed before the process ends (uncached memory that a kernel has read must
+stay allocated until then).
+
 --partition prices answering the 10^9-key stream part by part: the query
 over the same stream grouped by part (each part's 296 KB of pilots then
 stays in the L2), against the query over the shuffled stream, next to the
@@ -38,9 +45,12 @@ def main():
     ap.add_argument("--reps", type=int, default=4)
     ap.add_argument("--lines", action="store_true", help="line-size probe instead of the size sweep")
     ap.add_argument("--partition", action="store_true", help="price of querying part by part")
+    ap.add_argument("--memtypes", action="store_true", help="pure gather from default, fine-grained, uncached memory")
     args = ap.parse_args()
     if args.lines:
         return lines(args)
+    if args.memtypes:
+        return memtypes(args)
     if args.partition:
         return partition(args)
     n = int(args.n)
@@ -101,6 +111,52 @@ def lines(args):
         print(f"T={T >> 20:5d} MiB  single {row['single_ms']:.3f} ms  +o^32 {row['pair_xor32_ms']:.3f}  "
               f"+o^64 {row['pair_xor64_ms']:.3f}  +o^128 {row['pair_xor128_ms']:.3f} ms", flush=True)
         del table
+    print(json.dumps(res), flush=True)
+
+
+_KEEP = []  # tables allocated by memtypes(), held until the process ends
+
+
+def memtypes(args):
+    import ctypes as C
+
+    import torch
+
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipExtMallocWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_size_t, C.c_uint]
+    hip.hipExtMallocWithFlags.restype = C.c_int
+    hip.hipMemset.argtypes = [C.c_void_p, C.c_int, C.c_size_t]
+    hip.hipMemset.restype = C.c_int
+    T = SIZES[6]  # the pilot array of the 10^9-key MPHF
+    n = 1 << 28
+    torch.cuda.init()
+    sink = torch.empty(256 * 8192, dtype=torch.int32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"n": n, "table_bytes": T}
+    for name, flag in (("default", 0x0), ("finegrained", 0x1), ("uncached", 0x3)):
+        p = C.c_void_p()
+        if hip.hipExtMallocWithFlags(C.byref(p), T, flag) != 0 or not p.value:
+            raise SystemExit(f"hipExtMallocWithFlags({name}) failed")
+        _KEEP.append(p)
+        if hip.hipMemset(p, 0x5A, T) != 0:
+            raise SystemExit("hipMemset failed")
+
+        def run():
+            rc = P.lib().ptrhash_bench_gather_pure(n, p, T, C.c_void_p(sink.data_ptr()), sink.numel(), stream)
+            if rc:
+                raise SystemExit(f"gather failed: {rc}")
+
+        run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.reps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.reps
+        res[name] = {"ms": ms, "G_per_s": n / ms / 1e6}
+        print(f"{name:12s} {ms:.3f} ms  {n / ms / 1e6:.1f} G random bytes/s", flush=True)
     print(json.dumps(res), flush=True)
 
 

@@ -60,14 +60,14 @@ def _fake_db(path, rows):
 
 def test_traffic_counts_read_requests_by_size(tmp_path):
     # two dispatches: 1.0e9 and 1.1e9 128-byte line requests, a few 64- and
-    # 32-byte ones, 8e9 bytes written; DRAM requests reported beside them
+    # 32-byte ones, 8e9 bytes written; reads addressed to memory beside them
     reads = tmp_path / "r.db"
     write = tmp_path / "w.db"
     k = "ptrhash::query_pipelined<1, unsigned long>(...)"
     _fake_db(reads, [(k, "TCC_EA0_RDREQ_128B_sum", 1.0e9), (k, "TCC_EA0_RDREQ_128B_sum", 1.1e9),
                      (k, "TCC_EA0_RDREQ_64B_sum", 1e6), (k, "TCC_EA0_RDREQ_64B_sum", 1e6),
                      (k, "TCC_EA0_RDREQ_32B_sum", 2e6), (k, "TCC_EA0_RDREQ_32B_sum", 2e6),
-                     (k, "TCC_EA0_RDREQ_DRAM_sum", 0.9e9), (k, "TCC_EA0_RDREQ_DRAM_sum", 0.9e9),
+                     (k, "TCC_EA0_RDREQ_DRAM_32B_sum", 4.2e9), (k, "TCC_EA0_RDREQ_DRAM_32B_sum", 4.2e9),
                      ("ptrhash::bench_copy_k<1>(...)", "TCC_EA0_RDREQ_128B_sum", 62.5e6)])
     _fake_db(write, [("ptrhash::bench_copy_k<1>(...)", "WRITE_SIZE", 8e9 / 1024), (k, "WRITE_SIZE", 8e9 / 1024)])
     out = tmp_path / "t.json"
@@ -77,7 +77,7 @@ def test_traffic_counts_read_requests_by_size(tmp_path):
     assert res["read_bytes"] == pytest.approx(1.05e9 * 128 + 1e6 * 64 + 2e6 * 32)  # mean of the two dispatches
     assert res["write_bytes"] == pytest.approx(8e9)
     assert res["traffic_bytes_per_launch"] == pytest.approx(res["read_bytes"] + 8e9)
-    assert res["dram_read_requests"] == pytest.approx(0.9e9)
+    assert res["memory_read_bytes"] == pytest.approx(32 * 4.2e9)
     assert "L2" in res["level"]
     assert json.load(open(out))["kernel_source_sha256"] == profsum.kernel_source_hash()
 
