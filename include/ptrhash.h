@@ -417,8 +417,11 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
                                       void *remap, ptrhash_build_info *info, hipStream_t stream);
 
 /* As ptrhash_build_u64_gpu for byte strings in device memory: key i =
- * data[offsets[i] .. offsets[i+1]), data 8-byte aligned with at least 64
- * readable bytes after the last string (the layout the query takes). The
+ * data[offsets[i] .. offsets[i+1]), data 8-byte aligned, data_len bytes with
+ * at least 64 readable bytes after the last string (the layout the query
+ * takes). The offsets are checked on the device before any string is read:
+ * decreasing offsets, or a string ending later than data_len - 16, give
+ * E_INVAL. The
  * string hash depends on the seed, so every attempt hashes and sorts again;
  * equal hashes of distinct strings cause a reseed, equal strings E_DUPLICATE,
  * like ptrhash_build_bytes (same result, byte for byte). With 128-bit
@@ -430,13 +433,15 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
  * hashes) + 33*P*B + 5*P*S/8 + 20*(P*S - n) bytes plus 16*S bytes per
  * compute unit. Seeds
  * are searched one after the other. */
-PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, uint64_t data_len, const uint64_t *offsets, uint64_t n,
                                         ptrhash_params *params, uint8_t *pilots, void *remap,
                                         ptrhash_build_info *info, hipStream_t stream);
 
 /* As ptrhash_build_u64 for byte strings data[offsets[i] .. offsets[i+1])
- * (host memory); equal 64-bit hashes of distinct strings cause a reseed. */
-PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+ * (host memory, data_len bytes; offsets non-decreasing and at most data_len,
+ * else E_INVAL before any string is read); equal 64-bit hashes of distinct
+ * strings cause a reseed. */
+PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, uint64_t data_len, const uint64_t *offsets, uint64_t n,
                                     ptrhash_params *params, uint8_t *pilots, void *remap, int threads,
                                     ptrhash_build_info *info);
 

@@ -638,10 +638,16 @@ PTRHASH_API int ptrhash_build_u64(const uint64_t *keys, uint64_t n, ptrhash_para
     }
 }
 
-PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+PTRHASH_API int ptrhash_build_bytes(const uint8_t *data, uint64_t data_len, const uint64_t *offsets, uint64_t n,
                                     ptrhash_params *params, uint8_t *pilots, void *remap, int threads,
                                     ptrhash_build_info *info) {
     if (!data || !offsets) return ptrhash::set_error(PTRHASH_E_INVAL, "data/offsets is NULL");
+    for (uint64_t i = 0; i < n; ++i)
+        if (offsets[i + 1] < offsets[i])
+            return ptrhash::set_error(PTRHASH_E_INVAL, "offsets decrease at key %llu", (unsigned long long)i);
+    if (offsets[n] > data_len)
+        return ptrhash::set_error(PTRHASH_E_INVAL, "the strings end at %llu, past data_len %llu",
+                                  (unsigned long long)offsets[n], (unsigned long long)data_len);
     KeySource src;
     src.data = data;
     src.offsets = offsets;

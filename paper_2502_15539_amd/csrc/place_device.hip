@@ -1017,6 +1017,17 @@ __global__ void hash_strings128_gpu_k(const uint8_t *__restrict__ data, const ui
     }
 }
 
+// flag[0] = 1 if some key's offsets decrease or its end passes end_limit.
+__global__ void check_offsets_k(const uint64_t *__restrict__ offsets, uint64_t n, uint64_t end_limit,
+                                uint32_t *__restrict__ flag) {
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+        bad |= o1 < o0 || o1 > end_limit;
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
 // out[i] = src[idx[i]]
 __global__ void gather_k(const uint64_t *__restrict__ src, const uint64_t *__restrict__ idx, uint64_t n,
                          uint64_t *__restrict__ out) {
@@ -1729,11 +1740,15 @@ int equal_strings(const uint8_t *data, const uint64_t *offsets, const std::vecto
     return PTRHASH_OK;
 }
 
-int build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n, ptrhash_params *params,
-                    uint8_t *pilots, void *remap, ptrhash_build_info *info, hipStream_t stream) {
+int build_bytes_gpu(const uint8_t *data, uint64_t data_len, const uint64_t *offsets, uint64_t n,
+                    ptrhash_params *params, uint8_t *pilots, void *remap, ptrhash_build_info *info,
+                    hipStream_t stream) {
     using namespace ptrhash;
     if (!data || !offsets || !params || !pilots) return set_error(PTRHASH_E_INVAL, "NULL argument");
     if (reinterpret_cast<uintptr_t>(data) & 7u) return set_error(PTRHASH_E_INVAL, "data must be 8-byte aligned");
+    if (data_len < kBytesPadding)
+        return set_error(PTRHASH_E_INVAL, "data_len %llu is below the %llu bytes of padding",
+                         (unsigned long long)data_len, (unsigned long long)kBytesPadding);
     if (int rc = check_build_params(n, params, PTRHASH_KEY_BYTES)) return rc;
     if (ptrhash_remap_bytes(params) && !remap) return set_error(PTRHASH_E_INVAL, "remap is NULL");
     // 128-bit hashes: the high half picks part and bucket, the low half the
@@ -1754,6 +1769,19 @@ int build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n, pt
     }
     HIP_OR_FAIL(g.buffers().get(&pairs, 2 * kMaxPairs), "pairs");
     HIP_OR_FAIL(g.buffers().get(&npairs, 2), "pairs");
+    // the offsets are on the device: check them there before any string is read
+    {
+        HIP_OR_FAIL(hipMemsetAsync(npairs, 0, sizeof(uint32_t), stream), "memset");
+        hipLaunchKernelGGL(check_offsets_k, dim3(4096), dim3(256), 0, stream, offsets, n, bytes_end_limit(data_len),
+                           npairs);
+        HIP_OR_FAIL(hipGetLastError(), "offsets check launch");
+        uint32_t bad = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(&bad, npairs, sizeof bad, hipMemcpyDeviceToHost, stream), "copy out");
+        HIP_OR_FAIL(hipStreamSynchronize(stream), "sync");
+        if (bad)
+            return set_error(PTRHASH_E_INVAL, "offsets decrease, or a string ends later than data_len - %llu",
+                             (unsigned long long)kBytesReadSlack);
+    }
     std::vector<uint64_t> hpairs(2 * kMaxPairs);
     for (int attempt = 0; attempt < kMaxSeeds; ++attempt) {
         // the string hash depends on the seed: hash, sort and order per attempt
@@ -1823,11 +1851,11 @@ PTRHASH_API int ptrhash_build_u64_gpu(const uint64_t *keys, uint64_t n, ptrhash_
     }
 }
 
-PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, const uint64_t *offsets, uint64_t n,
+PTRHASH_API int ptrhash_build_bytes_gpu(const uint8_t *data, uint64_t data_len, const uint64_t *offsets, uint64_t n,
                                         ptrhash_params *params, uint8_t *pilots, void *remap,
                                         ptrhash_build_info *info, hipStream_t stream) {
     try {
-        return build_bytes_gpu(data, offsets, n, params, pilots, remap, info, stream);
+        return build_bytes_gpu(data, data_len, offsets, n, params, pilots, remap, info, stream);
     } catch (const std::bad_alloc &) {
         return ptrhash::set_error(PTRHASH_E_NOMEM, "host allocation failed during construction");
     }

@@ -121,9 +121,10 @@ _SIGS = {
                                            C.c_int, C.POINTER(BuildInfo), C.c_void_p]),
     "ptrhash_build_u64_gpu": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
                                         C.POINTER(BuildInfo), C.c_void_p]),
-    "ptrhash_build_bytes_gpu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p,
+    "ptrhash_build_bytes_gpu": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p,
                                           C.c_void_p, C.POINTER(BuildInfo), C.c_void_p]),
-    "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p, C.c_void_p,
+    "ptrhash_build_bytes": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.POINTER(Params), C.c_void_p,
+                                      C.c_void_p,
                                       C.c_int, C.POINTER(BuildInfo)]),
     "ptrhash_bench_gather": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_int,
                                        C.c_int, C.c_void_p]),
@@ -298,7 +299,7 @@ def build_bytes(data: np.ndarray, offsets: np.ndarray, params: Params | None = N
     pilots = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
     remap = np.zeros(remap_bytes(p), dtype=np.uint8)
     info = BuildInfo()
-    _check(lib().ptrhash_build_bytes(_np_ptr(data), _np_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
+    _check(lib().ptrhash_build_bytes(_np_ptr(data), data.size, _np_ptr(offsets), n, C.byref(p), _np_ptr(pilots),
                                      _np_ptr(remap), int(threads), C.byref(info)), "ptrhash_build_bytes")
     return Built(p, pilots, remap, info)
 
@@ -318,7 +319,8 @@ def build_bytes_device(data, offsets, params: Params | None = None, threads: int
     info = BuildInfo()
     if placement != "host":
         p = p0.copy()
-        rc = lib().ptrhash_build_bytes_gpu(_device_tensor(data, "data", 1, 0), _device_tensor(offsets, "offsets", 8, n + 1), n, C.byref(p), _np_ptr(pilots),
+        rc = lib().ptrhash_build_bytes_gpu(_device_tensor(data, "data", 1, 0), data.numel(),
+                                           _device_tensor(offsets, "offsets", 8, n + 1), n, C.byref(p), _np_ptr(pilots),
                                            _np_ptr(remap), C.byref(info), _stream(stream))
         if rc == 0:
             return Built(p, pilots, remap, info, "device")

@@ -81,7 +81,7 @@ int main() {
             while (data.size() % 8) data.push_back(0);
             ptrhash_params p = params(n, 3.5, 0, 0, PTRHASH_KEY_BYTES, false, hb);
             std::vector<uint8_t> pil(p.num_parts * p.buckets_per_part), rem(ptrhash_remap_bytes(&p) + 1);
-            int rc = ptrhash_build_bytes(data.data(), off.data(), n, &p, pil.data(), rem.data(), 4, nullptr);
+            int rc = ptrhash_build_bytes(data.data(), data.size(), off.data(), n, &p, pil.data(), rem.data(), 4, nullptr);
             if (rc) { std::printf("bytes n=%llu hb=%u rc=%d\n", (unsigned long long)n, hb, rc); ++fails; }
         }
     }

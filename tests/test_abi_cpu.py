@@ -242,12 +242,31 @@ def test_device_string_build_rejects_bad_arguments_before_any_device_call():
     pil = np.zeros(p.num_parts * p.buckets_per_part, dtype=np.uint8)
     rm = np.zeros(P.remap_bytes(p), dtype=np.uint8)
     f = P.lib().ptrhash_build_bytes_gpu
-    assert f(None, C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None, None) == P.E_INVAL
-    assert f(C.c_void_p(67), C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None,
-             None) == P.E_INVAL  # unaligned data
-    q = P.params_default(1000)  # u64-key params
-    assert f(C.c_void_p(64), C.c_void_p(64), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None,
+    assert f(None, 1 << 20, C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None,
              None) == P.E_INVAL
+    assert f(C.c_void_p(67), 1 << 20, C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None,
+             None) == P.E_INVAL  # unaligned data
+    assert f(C.c_void_p(64), 63, C.c_void_p(64), 1000, C.byref(p), pil.ctypes.data, rm.ctypes.data, None,
+             None) == P.E_INVAL  # no room for the padding
+    q = P.params_default(1000)  # u64-key params
+    assert f(C.c_void_p(64), 1 << 20, C.c_void_p(64), 1000, C.byref(q), pil.ctypes.data, rm.ctypes.data, None,
+             None) == P.E_INVAL
+
+
+def test_host_string_build_checks_offsets_before_reading():
+    """Decreasing offsets, or strings that end past data_len, are refused
+    with E_INVAL before any string is read."""
+    data, off = K.strings(1000, seed=2)
+    ok = P.build_bytes(data, off)
+    assert ok.params.n == 1000
+    bad = off.copy()
+    bad[500] = bad[499] - 1
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_bytes(data, bad)
+    assert e.value.code == P.E_INVAL
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_bytes(data[: int(off[-1]) - 1], off)
+    assert e.value.code == P.E_INVAL
 
 
 def test_builder_equals_oracle_one_huge_bucket():

@@ -296,6 +296,17 @@ def test_device_string_build_errors_and_host_agreement():
     with pytest.raises(P.PtrHashError) as e:
         P.build_bytes_device(*dev_strings(data2, off2), placement="device")
     assert e.value.code == P.E_DUPLICATE
+    # offsets checked on the device before any string is read
+    data3, off3 = K.strings(5000, seed=4)
+    bad = off3.copy()
+    bad[100] = bad[99] - 1
+    with pytest.raises(P.PtrHashError) as e:
+        P.build_bytes_device(*dev_strings(data3, bad), placement="device")
+    assert e.value.code == P.E_INVAL
+    d3, o3 = dev_strings(data3, off3)
+    with pytest.raises(P.PtrHashError) as e:  # the last string ends less than 16 bytes before the buffer does
+        P.build_bytes_device(d3[: int(off3[-1]) + 8], o3, placement="device")
+    assert e.value.code == P.E_INVAL
     # 128-bit string hashes: the device build equals the host build
     p = P.params_default(1000, key_kind=P.KEY_BYTES)
     p.hash_bits = 128
