@@ -242,6 +242,10 @@ def test_lambda4_linear_fails_quick():
 
 @pytest.mark.slow
 def test_lambda4_linear_fails_full_cap():
+    """The figure's own setting (S = 2^18) with the full 10*S cap: about 100 s
+    on one core, so it runs only with PTRHASH_SLOW=1. The cap itself is
+    pinned by default on a part of S = 2^11 in test_oracle_search_rules.py
+    (test_part_fails_right_after_ten_S_evictions)."""
     p, n = lambda4_params(O.GAMMA_LINEAR)
     with pytest.raises(O.BuildError):
         O.build_u64(K.u64_keys(n, seed=7), params=p, eviction_factor=10, max_attempts=1)
