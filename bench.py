@@ -191,7 +191,9 @@ def profiled_traffic(workload, ms, n):
     info = {"level": t.get("level", ""), "traffic_GBps": b / (ms / 1e3) / 1e9,
             "traffic_frac_of_peak": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic_bytes_per_key": b / n,
             "read_bytes": t.get("read_bytes"), "write_bytes": t.get("write_bytes"),
-            "memory_read_bytes": t.get("memory_read_bytes"), "source": os.path.relpath(path, ROOT)}
+            "memory_read_bytes": t.get("memory_read_bytes"),
+            "fetch_size_check": (t.get("fetch_size_check") or {}).get("fetch_bytes_scaled"),
+            "source": os.path.relpath(path, ROOT)}
     return b, info
 
 

@@ -11,7 +11,10 @@
         addressed to memory rather than to other agents
         (TCC_EA0_RDREQ_DRAM_32B_sum, in 32-byte units), which still include
         what the MALL on the memory side serves. The JSON records a hash of
-        the kernel sources so that a later change voids it.
+        the kernel sources so that a later change voids it. With --fetch DB
+        (a FETCH_SIZE run of the same command) it also records FETCH_SIZE
+        scaled by the factor that maps the copy kernel's FETCH_SIZE onto the
+        bytes it reads, as a cross-check of the read bytes.
     python -m paper_2502_15539_amd.profsum overlap DB --kernel SUBSTR
         from a kernel trace: dispatches of the kernel, the most running at
         one instant, the time-weighted mean number running while any runs,
@@ -106,6 +109,15 @@ def traffic(args) -> dict:
     other = {c: v for c, v in reads if not re.fullmatch(r"TCC_EA0_RDREQ_(\d+)B_sum", c)}
     other.pop("TCC_EA0_RDREQ_DRAM_32B_sum", None)
     other.pop("TCC_EA0_RDREQ_DRAM_sum", None)
+    fetch = None
+    if getattr(args, "fetch", None):
+        # cross-check: FETCH_SIZE scaled by the factor that maps a copy
+        # kernel's FETCH_SIZE onto the bytes it reads
+        copy_fetch = _mean(args.fetch, args.copy, "FETCH_SIZE") * 1024.0
+        scale = args.copy_bytes / copy_fetch
+        k_fetch = _mean(args.fetch, args.kernel, "FETCH_SIZE") * 1024.0
+        fetch = {"fetch_size_bytes_raw": k_fetch, "copy_kernel": args.copy, "copy_read_bytes": args.copy_bytes,
+                 "scale": scale, "fetch_bytes_scaled": k_fetch * scale}
     res = {"kernel": args.kernel,
            "level": "L2 to memory fabric: read requests by size plus WRITE_SIZE (includes MALL hits)",
            "read_requests_by_size": {f"{k}B": v for k, v in sorted(sized.items())},
@@ -113,6 +125,8 @@ def traffic(args) -> dict:
            "memory_read_bytes": None if dram32 is None else 32.0 * dram32,
            "read_requests": other.get("TCC_EA0_RDREQ_sum"),
            "traffic_bytes_per_launch": read_bytes + k_write, "kernel_source_sha256": kernel_source_hash()}
+    if fetch:
+        res["fetch_size_check"] = fetch
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     return res
@@ -186,6 +200,9 @@ def main():
     r.add_argument("--write", required=True, help="DB with WRITE_SIZE")
     r.add_argument("--kernel", required=True)
     r.add_argument("--out", required=True)
+    r.add_argument("--fetch", help="DB with FETCH_SIZE, for the copy-scaled cross-check")
+    r.add_argument("--copy", default="bench_copy_k<1>", help="copy kernel of the cross-check")
+    r.add_argument("--copy-bytes", type=float, default=8e9, help="bytes the copy kernel reads per launch")
     st = sub.add_parser("steps")
     st.add_argument("db")
     st.add_argument("--kernel", required=True)

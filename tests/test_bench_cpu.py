@@ -166,3 +166,17 @@ def test_timed_steps_are_the_last_before_the_rooflines():
     assert st["first_to_last_ms_per_step"] == pytest.approx((198e6 - 140e6) / 1e6 / 3)
     with pytest.raises(SystemExit):
         profsum.timed_steps(rows, "ptrhash::query_pipelined<1, unsigned long>", "bench_gather", 9)
+
+
+def test_traffic_fetch_size_cross_check(tmp_path):
+    k = "ptrhash::query_pipelined<1, unsigned long>(...)"
+    reads, write, fetch = tmp_path / "r.db", tmp_path / "w.db", tmp_path / "f.db"
+    _fake_db(reads, [(k, "TCC_EA0_RDREQ_128B_sum", 1e9)])
+    _fake_db(write, [(k, "WRITE_SIZE", 8e9 / 1024)])
+    _fake_db(fetch, [("ptrhash::bench_copy_k<1>(...)", "FETCH_SIZE", 4e9 / 1024), (k, "FETCH_SIZE", 64e9 / 1024)])
+    args = type("A", (), {"reads": str(reads), "write": str(write), "kernel": "query_pipelined<1, unsigned long>",
+                          "out": str(tmp_path / "t.json"), "fetch": str(fetch), "copy": "bench_copy_k<1>",
+                          "copy_bytes": 8e9})
+    res = profsum.traffic(args)
+    assert res["fetch_size_check"]["scale"] == pytest.approx(2.0)
+    assert res["fetch_size_check"]["fetch_bytes_scaled"] == pytest.approx(res["read_bytes"])
