@@ -7,10 +7,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <iterator>
 #include <mutex>
 #include <new>
-#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
