@@ -203,11 +203,12 @@ uint32_t handle_slot(MultiWork &w, const ptrhash_handle *h, uint32_t next, bool 
 namespace ptrhash {
 int fill_multi_table(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile) {
     uint32_t cap = 2;
-    while (cap < 2u * (uint32_t)(k > 0 ? k : 1)) cap <<= 1;
-    std::vector<MultiSpan> outs((size_t)(k > 0 ? k : 1));
+    const size_t kk = (size_t)(k > 0 ? k : 1);
+    while (cap < 2u * (uint32_t)kk) cap <<= 1;
+    std::vector<MultiSpan> outs(kk);
     std::vector<const ptrhash_handle *> handles(cap);
-    std::vector<uint32_t> index(cap);
-    MultiWork w{outs.data(), handles.data(), index.data(), cap};
+    std::vector<uint32_t> index(cap), batch_mphf(kk), mphf_start(kk + 1);
+    MultiWork w{outs.data(), handles.data(), index.data(), cap, batch_mphf.data(), mphf_start.data()};
     return fill_multi_table_ws(t, descs, k, tile, w);
 }
 
@@ -240,18 +241,29 @@ int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, u
     uint64_t *tb = multi_tile_begin(t);
     MultiBatch *bt = multi_batches(t);
     DevMphf *mp = multi_mphfs(t);
-    // each distinct handle once
+    // each distinct handle once, numbered in order of first appearance
     for (uint32_t i = 0; i < w.hcap; ++i) w.handles[i] = nullptr;
     uint32_t j = 0, mphfs = 0;
-    uint64_t tiles = 0;
     for (int i = 0; i < k; ++i) {
         const ptrhash_query_desc &d = descs[i];
         if (d.n_q == 0) continue;
         bool fresh = false;
         const uint32_t mi = handle_slot(w, d.handle, mphfs, &fresh);
         if (fresh) mp[mphfs++] = device_view(d.handle);
+        w.batch_mphf[j++] = mi;
+    }
+    // batches grouped by MPHF (a stable counting sort), so that the tiles
+    // of one MPHF are contiguous
+    for (uint32_t m = 0; m <= mphfs; ++m) w.mphf_start[m] = 0;
+    for (uint32_t b = 0; b < c; ++b) w.mphf_start[w.batch_mphf[b] + 1]++;
+    for (uint32_t m = 0; m < mphfs; ++m) w.mphf_start[m + 1] += w.mphf_start[m];
+    j = 0;
+    for (int i = 0; i < k; ++i) {
+        const ptrhash_query_desc &d = descs[i];
+        if (d.n_q == 0) continue;
+        const uint32_t mi = w.batch_mphf[j++];
         const bool bytes = d.handle->params.key_kind == PTRHASH_KEY_BYTES;
-        MultiBatch &b = bt[j];
+        MultiBatch &b = bt[w.mphf_start[mi]++];
         b.keys = bytes ? static_cast<const void *>(d.data) : static_cast<const void *>(d.keys);
         b.offsets = bytes ? d.offsets : nullptr;
         b.out = d.out;
@@ -259,8 +271,11 @@ int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, u
         b.end_limit = bytes ? bytes_end_limit(d.data_len) : 0;
         b.mphf = mi;
         b.flags = (bytes ? kBatchBytes : 0u) | (d.handle->params.index_bits == 64 ? kBatchOut64 : 0u);
-        tb[j++] = tiles;
-        tiles += (d.n_q + tile - 1) / tile;
+    }
+    uint64_t tiles = 0;
+    for (uint32_t b = 0; b < c; ++b) {
+        tb[b] = tiles;
+        tiles += (bt[b].nq + tile - 1) / tile;
     }
     t->mphfs = mphfs;
     t->tile = tile;

@@ -48,7 +48,9 @@ enum : uint32_t { kBatchBytes = 1, kBatchOut64 = 2 };
 // header: tile_begin[count] (first global tile of each batch, ascending),
 // batch[count], then mphf[mphfs] (each distinct MPHF once). The kernel's
 // binary search touches only the compact tile_begin array, and a table of
-// many batches over few MPHFs stays small to upload.
+// many batches over few MPHFs stays small to upload. Batches are grouped by
+// MPHF (in the order the MPHFs first appear), so that a contiguous range of
+// tiles touches few MPHFs.
 struct MultiTable {
     uint32_t count;  // batches
     uint32_t tile;   // keys per tile the table was numbered with
@@ -101,10 +103,12 @@ struct MultiSpan {
     int batch;
 };
 struct MultiWork {
-    MultiSpan *outs;
-    const ptrhash_handle **handles;
-    uint32_t *index;
+    MultiSpan *outs;                 // k
+    const ptrhash_handle **handles;  // hcap
+    uint32_t *index;                 // hcap
     uint32_t hcap;
+    uint32_t *batch_mphf;            // k: MPHF of each non-empty batch
+    uint32_t *mphf_start;            // k + 1: first slot of each MPHF's batches in the table
 };
 int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, uint32_t tile, MultiWork &w);
 

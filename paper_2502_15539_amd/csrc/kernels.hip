@@ -143,13 +143,20 @@ __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict_
     process_tile<K, OutT, true>(m, nullptr, data, offsets, end_limit, nq, out, base, blockDim.x);
 }
 
+// Compute dies (XCDs) of the device, each with its own L2; the dispatcher
+// hands consecutive workgroups to them in turn (workgroup i to die i mod 8).
+constexpr uint32_t kXcds = 8;
+
 // Persistent launch over a table of query batches (each against its own
 // resident MPHF). Every batch is cut into tiles of K*blockDim keys (the
 // table records the tile size it was numbered with); tiles are numbered
-// globally (tile_begin is a prefix sum) and the grid strides over them, so
-// batches of any mix of sizes share one launch. The header (batch count,
-// tile count) lives in device memory next to the batches, so a captured
-// launch can be replayed over new batches.
+// globally (tile_begin is a prefix sum), so batches of any mix of sizes
+// share one launch. The table groups the batches by MPHF, and the workgroups
+// of each die take one contiguous eighth of the tiles, so a die's L2 holds
+// the pilots and remap lines of about an eighth of the MPHFs instead of
+// all of them. The header (batch count, tile count) lives in device memory
+// next to the batches, so a captured launch can be replayed over new
+// batches.
 template <int K>
 __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict__ table) {
     const uint32_t count = table->count;
@@ -159,7 +166,14 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
     const uint64_t *__restrict__ tb = multi_tile_begin(table);
     const MultiBatch *__restrict__ bt = multi_batches(table);
     const DevMphf *__restrict__ mp = multi_mphfs(table);
-    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    uint64_t first = blockIdx.x, end = tiles, step = gridDim.x;
+    if (gridDim.x % kXcds == 0) {
+        const uint32_t x = blockIdx.x % kXcds;
+        first = tiles * x / kXcds + blockIdx.x / kXcds;
+        end = tiles * (x + 1) / kXcds;
+        step = gridDim.x / kXcds;
+    }
+    for (uint64_t t = first; t < end; t += step) {
         // last batch whose first tile is <= t (uniform across the block)
         uint32_t lo = 0, hi = count - 1;
         while (lo < hi) {

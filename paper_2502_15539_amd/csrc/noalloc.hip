@@ -36,6 +36,8 @@ alignas(256) uint8_t g_stage[kNoAllocBytes];  // the table as the host builds it
 MultiSpan g_outs[kNoAllocBatches];
 const ptrhash_handle *g_handles[kHandleSlots];
 uint32_t g_index[kHandleSlots];
+uint32_t g_batch_mphf[kNoAllocBatches];
+uint32_t g_mphf_start[kNoAllocBatches + 1];
 
 }  // namespace
 }  // namespace ptrhash
@@ -67,7 +69,7 @@ PTRHASH_API int ptrhash_query_multi_noalloc(const ptrhash_query_desc *descs, int
     }
     const MultiTuning t = multi_default_tuning();
     MultiTable *stage = reinterpret_cast<MultiTable *>(g_stage);
-    MultiWork w{g_outs, g_handles, g_index, kHandleSlots};
+    MultiWork w{g_outs, g_handles, g_index, kHandleSlots, g_batch_mphf, g_mphf_start};
     const int rc = fill_multi_table_ws(stage, descs, k, multi_tile(t), w);
     if (rc) return rc;
     if (stage->tiles == 0) return PTRHASH_OK;
