@@ -173,12 +173,23 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
         end = tiles * (x + 1) / kXcds;
         step = gridDim.x / kXcds;
     }
+    const uint32_t lane = __lane_id();
     for (uint64_t t = first; t < end; t += step) {
-        // last batch whose first tile is <= t (uniform across the block)
-        uint32_t lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) / 2;
-            if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+        // The last batch whose first tile is <= t, found by each wavefront
+        // with 64 reads in parallel per round: the lanes read every
+        // stride-th first tile of the remaining range and the highest lane
+        // whose tile is <= t narrows it to one stride (two rounds for 4096
+        // batches instead of twelve dependent reads). tb[0] = 0 <= t, so the
+        // ballot is never empty.
+        uint32_t lo = 0, n = count;
+        while (n > 1) {
+            const uint32_t stride = (n + 63) / 64;
+            const uint32_t off = lane * stride;
+            const bool le = off < n && tb[lo + off] <= t;
+            const uint64_t mask = __ballot(le);
+            const uint32_t hit = 63u - (uint32_t)__clzll(mask);
+            lo += hit * stride;
+            n = n - hit * stride < stride ? n - hit * stride : stride;
         }
         const MultiBatch &q = bt[lo];
         const DevMphf &m = mp[q.mphf];
