@@ -246,3 +246,30 @@ def test_multi_autotuner(tmp_path, monkeypatch):
     for g, q, out, want in bs:
         assert np.array_equal(host(out, 0), want)
     plan.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 64, 0), (1, 256, 2), (8, 128, 0)])
+def test_tile_split_over_dies_and_batch_search(shape):
+    """The multi launch gives each of the 8 dies a contiguous eighth of the
+    tiles and finds a tile's batch with rounds of 64 parallel reads. Tile
+    totals around multiples of 8 and below 8, and batch counts around
+    powers of 64 (1, 2, 63, 64, 65, 130, 4096), each batch equal to the
+    oracle's query of its MPHF, interleaved MPHFs included (the table groups
+    batches by MPHF)."""
+    items, _ = pool()
+    rng = np.random.default_rng(77)
+    plan = P.MultiPlan(4096)
+    plan.set_kernel(*shape)
+    tile = shape[0] * shape[1]
+    cases = [[tile * t] for t in (1, 3, 7, 8, 9, 15, 16, 17)]
+    cases += [[1] * c for c in (2, 63, 64, 65, 130)]
+    cases += [[int(x) for x in rng.integers(1, 200, size=4096)]]
+    for sizes in cases:
+        batches = [make_batch(items[(i * 7) % len(items)], rng, s) for i, s in enumerate(sizes)]
+        say(f"[multi] shape {shape}: {len(sizes)} batches, {sum(sizes)} keys")
+        plan.set([(g, src, out) for g, src, out, _ in batches])
+        plan.launch()
+        torch.cuda.synchronize()
+        for g, src, out, want in batches:
+            assert np.array_equal(host(out, 0), want)
+    plan.close()
