@@ -188,10 +188,11 @@ typedef struct ptrhash_query_desc {
 
 /*
  * A reusable launch plan: a device table of up to max_descs batches and a
- * pinned host staging copy of it. plan_set validates the batches and
- * writes the staging copy (host only). plan_launch enqueues on stream an
- * asynchronous copy of the staging table to the device table followed by
- * one persistent kernel that strides over the tiles of every batch; the
+ * pinned, mapped host staging copy of it. plan_set validates the batches
+ * and writes the staging copy (host only). plan_launch enqueues on stream
+ * a small kernel that copies the staging table into the device table (on
+ * the stream itself, with no copy-engine hand-off), followed by one
+ * persistent kernel that strides over the tiles of every batch; the
  * result of each batch equals a separate ptrhash_query/ptrhash_query_bytes
  * call. plan_launch may be captured into a HIP graph: when the stream is
  * capturing it copies the whole table, so each replay runs the batches the

@@ -27,7 +27,8 @@ struct ptrhash_handle {
 struct ptrhash_multi_plan {
     int max = 0;
     MultiTable *d_table = nullptr;  // device copy read by the kernel
-    MultiTable *h_stage = nullptr;  // pinned host staging copy
+    MultiTable *h_stage = nullptr;  // pinned, mapped host staging copy
+    void *v_stage = nullptr;        // its device address
     size_t used_bytes = 0;
     ptrhash::MultiTuning tuning;
     uint32_t grid = 0;
@@ -551,16 +552,18 @@ PTRHASH_API int ptrhash_multi_plan_create(int max_descs, ptrhash_multi_plan **ou
     ptrhash_multi_plan *p = new (std::nothrow) ptrhash_multi_plan();
     if (!p) return fail(PTRHASH_E_NOMEM, "plan allocation failed");
     p->max = max_descs;
-    const size_t bytes = multi_table_capacity(max_descs);
+    // rounded up for the 16-byte copy of the stage-in kernel
+    const size_t bytes = (multi_table_capacity(max_descs) + 255) & ~(size_t)255;
     hipError_t e = hipMalloc(&p->d_table, bytes);
     if (e != hipSuccess) {
         p->d_table = nullptr;
         ptrhash_multi_plan_destroy(p);
         return fail(PTRHASH_E_NOMEM, "hipMalloc for the batch table: %s", hipGetErrorString(e));
     }
-    e = hipHostMalloc(&p->h_stage, bytes, hipHostMallocDefault);
+    e = hipHostMalloc(&p->h_stage, bytes, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) p->h_stage = nullptr;
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&p->v_stage, p->h_stage, 0);
     if (e != hipSuccess) {
-        p->h_stage = nullptr;
         ptrhash_multi_plan_destroy(p);
         return fail(PTRHASH_E_NOMEM, "hipHostMalloc for the staging table: %s", hipGetErrorString(e));
     }
@@ -617,7 +620,7 @@ PTRHASH_API int ptrhash_multi_plan_launch(ptrhash_multi_plan *plan, hipStream_t 
     if (!capturing && plan->h_stage->tiles == 0) return PTRHASH_OK;
     // a captured copy must cover any later table, so it copies all of it
     const size_t bytes = capturing ? multi_table_capacity(plan->max) : plan->used_bytes;
-    e = hipMemcpyAsync(plan->d_table, plan->h_stage, bytes, hipMemcpyHostToDevice, stream);
+    e = launch_stage_in(plan->v_stage, plan->d_table, bytes, stream);
     if (e != hipSuccess) return hip_fail(e, "batch table copy");
     e = launch_query_multi(plan->d_table, plan->tuning, plan->grid, stream);
     return e == hipSuccess ? PTRHASH_OK : hip_fail(e, "query_multi launch");

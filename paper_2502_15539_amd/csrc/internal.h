@@ -87,8 +87,14 @@ constexpr size_t multi_table_capacity(int max_batches) {
     return multi_table_bytes(m, m);
 }
 
+// Dynamic LDS of a multi-MPHF launch: 64 u64 per wavefront for the packed
+// remap decode.
+inline uint32_t multi_lds_bytes(const MultiTuning &t) { return (uint32_t)t.block / 64u * 64u * 8u; }
 // The table must have been filled with multi_tile(t); grid from multi_grid(t).
 hipError_t launch_query_multi(const MultiTable *table, const MultiTuning &t, uint32_t grid, hipStream_t s);
+// Copy bytes (rounded up to a multiple of 16, which both buffers must hold)
+// from mapped host memory src to device memory dst with a kernel on s.
+hipError_t launch_stage_in(const void *src, void *dst, size_t bytes, hipStream_t s);
 int multi_blocks_per_cu(const MultiTuning &t);  // most resident workgroups of the kernel per compute unit
 uint32_t multi_grid(const MultiTuning &t);      // persistent grid size on the current device
 // Validate k batches and write them (and the tile prefix sums for tiles of

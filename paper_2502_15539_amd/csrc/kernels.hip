@@ -17,27 +17,28 @@
 //    evict pilots from the L2 and MALL.
 //  - query_bytes<K>: the same for packed byte-string keys.
 //  - query_multi: a persistent launch over many batches, each against its
-//    own resident MPHF, described by a table in device memory.
+//    own resident MPHF, described by a table in device memory (stage_in_k
+//    copies a plan's table there from mapped host memory).
 #include "internal.h"
 #include "mphf_device.h"
 
 namespace ptrhash {
 
 template <typename T>
-__device__ __forceinline__ T nt_load(const T *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ T nt_load(const T *p) { return __builtin_nontemporal_load(gbl(p)); }
 
 template <typename OutT>
-__device__ __forceinline__ void nt_store(OutT v, OutT *p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(OutT v, OutT *p) { __builtin_nontemporal_store(v, gbl(p)); }
 
 template <typename OutT>
 __global__ void __launch_bounds__(1024) query_plain(const uint64_t *__restrict__ keys, uint64_t nq,
                                                     OutT *__restrict__ out, DevMphf m) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq) return;
-    const uint64_t h = hash_u64(keys[i]);
+    const uint64_t h = hash_u64(gbl(keys)[i]);
     uint32_t part;
     const uint64_t b = bucket_of(m, h, part);
-    uint64_t v = slot_of(m, h, part, m.pilots[b]);
+    uint64_t v = slot_of(m, h, part, gbl(m.pilots)[b]);
     if (m.remap_kind != kRemapNone && v >= m.n) v = remap_lookup(m, v);
     out[i] = (OutT)v;
 }
@@ -54,7 +55,7 @@ __device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], con
         const uint32_t *R = reinterpret_cast<const uint32_t *>(m.remap);
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (need[j]) v[j] = R[v[j] - m.n];
+            if (need[j]) v[j] = gbl(R)[v[j] - m.n];
         return;
     }
     ClefRead r[K];
@@ -72,15 +73,53 @@ __device__ __forceinline__ void finish_k(const DevMphf &m, uint64_t (&v)[K], con
         if (need[j]) v[j] = clef_value(r[j], idx[j]);
 }
 
+// The same with the wavefront's keys that need a remap entry packed onto
+// consecutive lanes: each round decodes up to 64 of them with every lane
+// busy, instead of one divergent pass per key slot j. When a few percent of
+// the keys are remapped (9 % over a fleet of small MPHFs), nearly every
+// wavefront has some lane to decode in every pass, so this saves K - 1 of
+// K passes. pack: 64 u64 of LDS owned by the wavefront; all its lanes must
+// be active.
+template <int K>
+__device__ __forceinline__ void finish_packed(const DevMphf &m, uint64_t (&v)[K], const bool (&ok)[K],
+                                              uint64_t *pack) {
+    if (m.remap_kind == kRemapNone) return;
+    bool need[K];
+    uint32_t pos[K];  // place in the wavefront's list of keys to decode
+    uint32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        need[j] = ok[j] && v[j] >= m.n;
+        const uint64_t mask = __ballot(need[j]);
+        pos[j] = total + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        total += (uint32_t)__popcll(mask);
+    }
+    const uint32_t lane = __lane_id();
+    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (need[j] && pos[j] - r0 < 64u) pack[pos[j] - r0] = v[j];
+        __builtin_amdgcn_wave_barrier();
+        if (r0 + lane < total) pack[lane] = remap_lookup(m, pack[lane]);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (need[j] && pos[j] - r0 < 64u) v[j] = pack[pos[j] - r0];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // One tile of K*stride keys starting at base: lane tid handles keys
 // base + tid + j*stride, j < K. Bytes selects packed byte-string keys; a
 // string may end at most at end_limit, and one whose offsets decrease or
-// pass that limit is not read and gets an index of all ones.
-template <int K, typename OutT, bool Bytes>
+// pass that limit is not read and gets an index of all ones. Packed decodes
+// the remap entries with finish_packed (pack: the wavefront's 64 u64 of
+// LDS).
+template <int K, typename OutT, bool Bytes, bool Packed = false>
 __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *__restrict__ keys,
                                              const uint8_t *__restrict__ data, const uint64_t *__restrict__ offsets,
                                              uint64_t end_limit, uint64_t nq, OutT *__restrict__ out, uint64_t base,
-                                             uint32_t stride) {
+                                             uint32_t stride, uint64_t *pack = nullptr) {
     uint64_t h[K], hs[K];  // hash for part/bucket, hash for the slot
     bool ok[K], bad[K];
     if (Bytes) {
@@ -91,7 +130,7 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
             bad[j] = false;
             h[j] = hs[j] = 0;
             if (ok[j]) {
-                const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
+                const uint64_t o0 = gbl(offsets)[i], o1 = gbl(offsets)[i + 1];
                 bad[j] = o1 < o0 || o1 > end_limit;
                 if (!bad[j]) h[j] = hash_bytes(m.seed, data, o0, o1 - o0, m.hash128 != 0, hs[j]);
             }
@@ -116,11 +155,14 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
     // unconditional too.
     uint32_t part[K], pil[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) pil[j] = m.pilots[bucket_of(m, h[j], part[j])];
+    for (int j = 0; j < K; ++j) pil[j] = gbl(m.pilots)[bucket_of(m, h[j], part[j])];
     uint64_t v[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) v[j] = slot_of(m, hs[j], part[j], pil[j]);
-    finish_k<K>(m, v, ok);
+    if (Packed)
+        finish_packed<K>(m, v, ok, pack);
+    else
+        finish_k<K>(m, v, ok);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint64_t i = base + (uint64_t)j * stride;
@@ -156,13 +198,16 @@ constexpr uint32_t kXcds = 8;
 // the pilots and remap lines of about an eighth of the MPHFs instead of
 // all of them. The header (batch count, tile count) lives in device memory
 // next to the batches, so a captured launch can be replayed over new
-// batches.
+// batches. Remap entries are decoded packed (finish_packed), in 64 u64 of
+// dynamic LDS per wavefront (multi_lds_bytes).
 template <int K>
 __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict__ table) {
     const uint32_t count = table->count;
     const uint64_t tiles = table->tiles;
     const uint32_t tile = table->tile;
     if (tile != (uint32_t)K * blockDim.x) return;  // table numbered for another launch shape
+    extern __shared__ uint64_t multi_pack[];
+    uint64_t *pack = multi_pack + (threadIdx.x / 64u) * 64u;
     const uint64_t *__restrict__ tb = multi_tile_begin(table);
     const MultiBatch *__restrict__ bt = multi_batches(table);
     const DevMphf *__restrict__ mp = multi_mphfs(table);
@@ -197,21 +242,31 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
         if (q.flags & kBatchBytes) {
             const uint8_t *data = static_cast<const uint8_t *>(q.keys);
             if (q.flags & kBatchOut64)
-                process_tile<K, uint64_t, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
-                                                static_cast<uint64_t *>(q.out), base, blockDim.x);
+                process_tile<K, uint64_t, true, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
+                                                      static_cast<uint64_t *>(q.out), base, blockDim.x, pack);
             else
-                process_tile<K, uint32_t, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
-                                                static_cast<uint32_t *>(q.out), base, blockDim.x);
+                process_tile<K, uint32_t, true, true>(m, nullptr, data, q.offsets, q.end_limit, q.nq,
+                                                      static_cast<uint32_t *>(q.out), base, blockDim.x, pack);
         } else {
             const uint64_t *keys = static_cast<const uint64_t *>(q.keys);
             if (q.flags & kBatchOut64)
-                process_tile<K, uint64_t, false>(m, keys, nullptr, nullptr, 0, q.nq, static_cast<uint64_t *>(q.out),
-                                                 base, blockDim.x);
+                process_tile<K, uint64_t, false, true>(m, keys, nullptr, nullptr, 0, q.nq,
+                                                       static_cast<uint64_t *>(q.out), base, blockDim.x, pack);
             else
-                process_tile<K, uint32_t, false>(m, keys, nullptr, nullptr, 0, q.nq, static_cast<uint32_t *>(q.out),
-                                                 base, blockDim.x);
+                process_tile<K, uint32_t, false, true>(m, keys, nullptr, nullptr, 0, q.nq,
+                                                       static_cast<uint32_t *>(q.out), base, blockDim.x, pack);
         }
     }
+}
+
+// The batch table copied from mapped host memory into device memory by a
+// kernel on the launch's own stream. A copy-engine transfer instead needs a
+// hand-off between the copy and compute queues before every launch (about
+// 20-60 us per step, the copy itself being 10 us).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) stage_in_k(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n16) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+        gbl(dst)[i] = gbl(src)[i];
 }
 
 // ---- launchers ----
@@ -315,17 +370,26 @@ static hipError_t with_multi_kernel(int K, F &&f) {
 int multi_blocks_per_cu(const MultiTuning &t) {
     int blocks = 0;
     const hipError_t e = with_multi_kernel(t.keys_per_lane, [&](auto kern) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, t.block, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, t.block, multi_lds_bytes(t));
     });
     return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
 
 hipError_t launch_query_multi(const MultiTable *table, const MultiTuning &t, uint32_t grid, hipStream_t s) {
     const hipError_t e = with_multi_kernel(t.keys_per_lane, [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3((uint32_t)t.block), 0, s, table);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3((uint32_t)t.block), multi_lds_bytes(t), s, table);
         return hipSuccess;
     });
     return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_stage_in(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const uint64_t n16 = (bytes + 15) / 16;
+    if (n16 == 0) return hipSuccess;
+    const uint64_t blocks = (n16 + 255) / 256 < 1024 ? (n16 + 255) / 256 : 1024;
+    hipLaunchKernelGGL(stage_in_k, dim3((uint32_t)blocks), dim3(256), 0, s, static_cast<const u32x4 *>(src),
+                       static_cast<u32x4 *>(dst), n16);
+    return hipGetLastError();
 }
 
 }  // namespace ptrhash

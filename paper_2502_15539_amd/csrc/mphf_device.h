@@ -12,6 +12,21 @@
 
 namespace ptrhash {
 
+// Global-memory views of pointers. Everything the queries read or write
+// (keys, pilots, remap, outputs, batch tables) is device memory or mapped
+// host memory, never LDS or scratch. Pointers that reach a kernel through a
+// table in memory are otherwise generic, and a generic (flat) access counts
+// against the LDS/scalar wait counter as well as the vector one, so that a
+// wait for a scalar table read also waits for every pilot gather in flight.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gbl(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gbl(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // FxHash mixing constant (odd, so x -> C*x is a bijection of u64).
 constexpr uint64_t kMix = 0x517cc1b727220a95ull;
 
@@ -124,15 +139,16 @@ __device__ __forceinline__ void clef_index(uint64_t j, uint64_t &line, uint32_t 
 
 __device__ __forceinline__ ClefRead clef_load(const uint8_t *remap, uint64_t line, uint32_t i) {
     const uint8_t *L = remap + line * 64u;
-    const uint4 a = *reinterpret_cast<const uint4 *>(L);          // off, bits 0..95
-    const uint32_t d4 = *reinterpret_cast<const uint32_t *>(L + 16);  // bits 96..127
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 a = *gbl(reinterpret_cast<const u32x4 *>(L));           // off, bits 0..95
+    const uint32_t d4 = *gbl(reinterpret_cast<const uint32_t *>(L + 16));  // bits 96..127
     ClefRead r;
     r.off = a.x;
     r.b0 = a.y;
     r.b1 = a.z;
     r.b2 = a.w;
     r.b3 = d4;
-    r.low = L[20 + i];
+    r.low = gbl(L)[20 + i];
     return r;
 }
 
@@ -147,7 +163,7 @@ __device__ __forceinline__ uint64_t clef_value(const ClefRead &r, uint32_t i) {
 
 __device__ __forceinline__ uint64_t remap_lookup(const DevMphf &m, uint64_t slot) {
     const uint64_t j = slot - m.n;
-    if (m.remap_kind == kRemapU32) return reinterpret_cast<const uint32_t *>(m.remap)[j];
+    if (m.remap_kind == kRemapU32) return gbl(reinterpret_cast<const uint32_t *>(m.remap))[j];
     uint64_t line;
     uint32_t i;
     clef_index(j, line, i);
@@ -175,7 +191,7 @@ __device__ __forceinline__ uint64_t hash_bytes(uint64_t seed, const uint8_t *dat
                                                bool wide, uint64_t &lo) {
     uint64_t st = seed ^ (len * kMix);
     uint64_t st2 = (seed ^ kWideSalt) ^ (len * kMix);
-    const uint64_t *W = reinterpret_cast<const uint64_t *>(data + (o0 & ~7ull));
+    const auto W = gbl(reinterpret_cast<const uint64_t *>(data + (o0 & ~7ull)));
     const uint32_t sh = (uint32_t)(o0 & 7u) * 8u;
     uint64_t cur = W[0];
     const uint64_t nw = (len + 7) >> 3;

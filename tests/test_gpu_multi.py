@@ -273,3 +273,49 @@ def test_tile_split_over_dies_and_batch_search(shape):
         for g, src, out, want in batches:
             assert np.array_equal(host(out, 0), want)
     plan.close()
+
+
+_packed = None
+
+
+def packed_pool():
+    """MPHFs whose slot >= n share is about one half (n = 130,000 just past
+    one part of 2^17 slots, so two parts), with each remap kind, and a byte
+    key one."""
+    global _packed
+    if _packed is None:
+        items = []
+        keys = K.u64_keys(130_000, seed=4242)
+        m = O.build_u64(keys)
+        frac = float(np.mean(O.query_u64(m, keys, O.REMAP_NONE) >= m.params.n))
+        for remap, bits in [(P.REMAP_CLEF, 32), (P.REMAP_U32, 64)]:
+            items.append(("u64", keys, m, load(m, remap, bits), remap, bits))
+        data, off = K.strings(130_000, seed=4343)
+        mb = O.build_bytes(data, off)
+        items.append(("bytes", (data, off), mb, load(mb, P.REMAP_CLEF, 32, key_kind=P.KEY_BYTES), P.REMAP_CLEF, 32))
+        _packed = (items, frac)
+    return _packed
+
+
+@pytest.mark.parametrize("shape", [(8, 64, 0), (8, 256, 0), (1, 64, 0), (2, 128, 4)])
+def test_packed_remap_decode_over_several_rounds(shape):
+    """The multi launch decodes a wavefront's remap entries packed onto its
+    lanes, 64 per round. With about half of the keys remapped and 8 keys per
+    lane, a wavefront has about 256 entries to decode (four rounds, the last
+    one partial); with 1 key per lane, about 32 (one partial round). Every
+    index equals the oracle's, members and non-members, for both remap
+    encodings and byte keys."""
+    items, frac = packed_pool()
+    say(f"[multi] packed remap: slot >= n share {frac:.3f}, shape {shape}")
+    assert frac > 0.3
+    rng = np.random.default_rng(91)
+    plan = P.MultiPlan(64)
+    plan.set_kernel(*shape)
+    sizes = [130_000, 1, 63, 64, 65, 4097, 20_000]
+    batches = [make_batch(items[i % len(items)], rng, s) for i, s in enumerate(sizes)]
+    plan.set([(g, src, out) for g, src, out, _ in batches])
+    plan.launch()
+    torch.cuda.synchronize()
+    for g, src, out, want in batches:
+        assert np.array_equal(host(out, 0), want)
+    plan.close()
