@@ -87,9 +87,13 @@ constexpr size_t multi_table_capacity(int max_batches) {
     return multi_table_bytes(m, m);
 }
 
-// Dynamic LDS of a multi-MPHF launch: 64 u64 per wavefront for the packed
-// remap decode.
-inline uint32_t multi_lds_bytes(const MultiTuning &t) { return (uint32_t)t.block / 64u * 64u * 8u; }
+// LDS of the packed remap decode: 64 u64 per wavefront of a workgroup of
+// `block` threads. The single-MPHF kernels pack from kPackMinKeys keys per
+// lane on (with fewer, a wavefront has at most one or two decode passes to
+// merge), the multi-MPHF kernel always.
+constexpr int kPackMinKeys = 4;
+inline uint32_t pack_lds_bytes(uint32_t block) { return block / 64u * 64u * 8u; }
+inline uint32_t multi_lds_bytes(const MultiTuning &t) { return pack_lds_bytes((uint32_t)t.block); }
 // The table must have been filled with multi_tile(t); grid from multi_grid(t).
 hipError_t launch_query_multi(const MultiTable *table, const MultiTuning &t, uint32_t grid, hipStream_t s);
 // Copy bytes (rounded up to a multiple of 16, which both buffers must hold)

@@ -173,16 +173,20 @@ __device__ __forceinline__ void process_tile(const DevMphf &m, const uint64_t *_
 template <int K, typename OutT>
 __global__ void __launch_bounds__(1024) query_pipelined(const uint64_t *__restrict__ keys, uint64_t nq,
                                                         OutT *__restrict__ out, DevMphf m) {
+    extern __shared__ uint64_t tile_pack[];  // 64 u64 per wavefront when packing
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    process_tile<K, OutT, false>(m, keys, nullptr, nullptr, 0, nq, out, base, blockDim.x);
+    process_tile<K, OutT, false, (K >= kPackMinKeys)>(m, keys, nullptr, nullptr, 0, nq, out, base, blockDim.x,
+                                                      tile_pack + (threadIdx.x / 64u) * 64u);
 }
 
 template <int K, typename OutT>
 __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict__ data, uint64_t end_limit,
                                                       const uint64_t *__restrict__ offsets, uint64_t nq,
                                                       OutT *__restrict__ out, DevMphf m) {
+    extern __shared__ uint64_t tile_pack[];  // 64 u64 per wavefront when packing
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * K + threadIdx.x;
-    process_tile<K, OutT, true>(m, nullptr, data, offsets, end_limit, nq, out, base, blockDim.x);
+    process_tile<K, OutT, true, (K >= kPackMinKeys)>(m, nullptr, data, offsets, end_limit, nq, out, base, blockDim.x,
+                                                     tile_pack + (threadIdx.x / 64u) * 64u);
 }
 
 // Compute dies (XCDs) of the device, each with its own L2; the dispatcher
@@ -280,6 +284,13 @@ static inline uint64_t keys_per_launch(uint32_t block, int K) {
     return (uint64_t)(0x80000000u / block) * block * (uint64_t)K;
 }
 
+// Dynamic LDS of a single-MPHF launch: the occupancy cap's reservation, at
+// least the packed decode's 64 u64 per wavefront when the kernel packs.
+static inline uint32_t launch_lds(const Tuning &t, int K) {
+    const uint32_t pack = K >= kPackMinKeys ? pack_lds_bytes((uint32_t)t.block) : 0u;
+    return t.lds_bytes > pack ? t.lds_bytes : pack;
+}
+
 template <typename OutT>
 static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t nq, void *out, const Tuning &t,
                                hipStream_t s) {
@@ -287,6 +298,7 @@ static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t 
     const uint32_t blk = (uint32_t)t.block;
     const int K = t.kernel == kKernelPlain ? 1 : t.keys_per_lane;
     const uint64_t chunk = keys_per_launch(blk, K);
+    const uint32_t lds = launch_lds(t, K);
     for (uint64_t s0 = 0; s0 < nq; s0 += chunk) {
         const uint64_t n = nq - s0 < chunk ? nq - s0 : chunk;
         const dim3 grid((uint32_t)ceil_div(n, (uint64_t)blk * K));
@@ -296,7 +308,7 @@ static hipError_t launch_u64_t(const DevMphf &m, const uint64_t *keys, uint64_t 
             switch (K) {
 #define PTRHASH_CASE(KK)                                                                                      \
     case KK:                                                                                                  \
-        hipLaunchKernelGGL((query_pipelined<KK, OutT>), grid, dim3(blk), t.lds_bytes, s, keys + s0, n, o + s0, m); \
+        hipLaunchKernelGGL((query_pipelined<KK, OutT>), grid, dim3(blk), lds, s, keys + s0, n, o + s0, m);         \
         break;
                 PTRHASH_CASE(1)
                 PTRHASH_CASE(2)
@@ -326,13 +338,14 @@ static hipError_t launch_bytes_t(const DevMphf &m, const uint8_t *data, uint64_t
     const uint32_t blk = (uint32_t)t.block;
     const int K = t.kernel == kKernelPlain ? 1 : t.keys_per_lane;
     const uint64_t chunk = keys_per_launch(blk, K);
+    const uint32_t lds = launch_lds(t, K);
     for (uint64_t s0 = 0; s0 < nq; s0 += chunk) {
         const uint64_t n = nq - s0 < chunk ? nq - s0 : chunk;
         const dim3 grid((uint32_t)ceil_div(n, (uint64_t)blk * K));
         switch (K) {
 #define PTRHASH_CASE(KK)                                                                                      \
     case KK:                                                                                                  \
-        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), grid, dim3(blk), t.lds_bytes, s, data, end_limit,       \
+        hipLaunchKernelGGL((query_bytes_k<KK, OutT>), grid, dim3(blk), lds, s, data, end_limit,               \
                            offsets + s0, n, o + s0, m);                                                       \
         break;
             PTRHASH_CASE(1)
