@@ -113,6 +113,12 @@ SERVER_CONFIGS = [  # (streams, slot_keys, copy_threads, zero_copy, mapped reque
     (4, 1 << 20, 12, 1, 0), (2, 1 << 22, 0, 1, 1), (4, 1 << 20, 0, 1, 1), (8, 1 << 20, 0, 1, 1),
 ]
 
+# Launch shapes tried for the chosen server configuration (keys per lane,
+# block, resident workgroups per CU; 0 = no cap). A zero-copy launch reads
+# its keys over PCIe and may want more wavefronts in flight than the shape
+# tuned on device-resident batches.
+SERVER_SHAPES = [(2, 64, 0), (4, 64, 0), (8, 64, 0), (4, 128, 0), (8, 128, 0), (4, 256, 0)]
+
 
 def mapped_copies(reqs):
     """The same requests with keys and outputs in one mapped pinned buffer
@@ -202,8 +208,26 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
     streams, slot, copiers, zc, mp = best
     sat = tried[best]
     rq = mreqs if mp else reqs
+    # then its launch shape, by the saturated rate again (and the light-load
+    # latency of a new winner)
+    shape_rates = {tuple(shape): sat["req_per_s"]}
+    for sh in SERVER_SHAPES:
+        if sh in shape_rates:
+            continue
+        srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
+                       copy_threads=copiers, zero_copy=zc, multi_kernel=sh)
+        run_server(srv, rq[:500], np.zeros(500), mp)
+        r = run_server(srv, rq, np.zeros(len(rq)), mp)
+        if r["req_per_s"] > sat["req_per_s"]:
+            light = run_server(srv, rq[:5000], poisson_arrivals(5000, 0.25 * r["req_per_s"], seed=99), mp)
+            r["light_p50_us"], r["light_p99_us"] = light["p50_us"], light["p99_us"]
+            sat = r
+        srv.close()
+        shape_rates[sh] = r["req_per_s"]
+        log(f"[serve] launch shape {sh}: {r['req_per_s']:.0f} req/s {r['keys_per_s'] / 1e9:.2f} G keys/s")
+    served_shape = max(shape_rates, key=shape_rates.get)
     srv = P.Server(streams=streams, max_batches=1024, slot_keys=slot, max_queued_keys=1 << 31,
-                   copy_threads=copiers, zero_copy=zc, multi_kernel=shape)
+                   copy_threads=copiers, zero_copy=zc, multi_kernel=served_shape)
     run_server(srv, rq[:500], np.zeros(500), mp)
     log(f"[serve] saturated: {sat['req_per_s']:.0f} req/s, {sat['keys_per_s'] / 1e9:.2f} G keys/s")
     runs = []
@@ -229,7 +253,8 @@ def run_c5(torch, n_requests=20000, loads=(0.25, 0.5, 0.8, 1.0, 1.2), threads=0,
             "served_equals_plain": agree,
             "mphfs": len(fleet), "resident_keys": int(sum(len(f[0]) for f in fleet)),
             "server_config": {"streams": streams, "slot_keys": slot, "copy_threads": copiers, "zero_copy": zc,
-                              "mapped_requests": mp, "max_batches": 1024, "multi_shape": list(shape)},
+                              "mapped_requests": mp, "max_batches": 1024, "multi_shape": list(served_shape)},
+            "server_shape_sweep_req_per_s": {f"{k[0]}/{k[1]}/{k[2]}": v for k, v in shape_rates.items()},
             "saturated_copied_requests": tried[best_copied],
             "config_sweep": {f"streams={c[0]},slot={c[1]},copiers={c[2]},zero_copy={c[3]},mapped={c[4]}":
                              {"req_per_s": v["req_per_s"], "keys_per_s": v["keys_per_s"],
