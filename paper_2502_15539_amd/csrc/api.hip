@@ -187,6 +187,24 @@ int check_batch_overlaps(const ptrhash_query_desc *descs, int k, MultiSpan *outs
 
 // Slot of handle h in the open-addressing table of w (inserted with index
 // `next` if absent; *fresh tells which).
+// Relative work of a batch in a multi-MPHF launch: 1 per key, plus
+// kRemapCost for the expected share of its keys that are remapped (slot >=
+// n: the share of slots at or past n in the MPHF's geometry), plus
+// kPilotCost times the MPHF's pilot bytes over a die's 4 MB L2 (at most 1),
+// which stands in for the pilot gathers that miss the L2. The weights are a
+// least-squares fit of the per-die run times (workgroup clocks) of the
+// 4096-request, 64-MPHF mix under two different splits (residuals within
+// 3.5 us of 140-160 us).
+constexpr double kRemapCost = 1.7, kPilotCost = 0.45, kDieL2Bytes = 4.0 * (1 << 20);
+double multi_batch_cost(const MultiBatch &b, const DevMphf &m) {
+    const double per_part = m.reduce_kind == kReduceMod ? (double)m.mod_slots : (double)(1ull << m.log2_slots);
+    const double slots = (double)m.parts * per_part;
+    const double remapped = m.remap_kind == kRemapNone || slots <= 0 ? 0.0 : (slots - (double)m.n) / slots;
+    const double pilots = (double)m.parts * (double)m.buckets;
+    const double l2 = pilots < kDieL2Bytes ? pilots / kDieL2Bytes : 1.0;
+    return (double)b.nq * (1.0 + kRemapCost * remapped + kPilotCost * l2);
+}
+
 uint32_t handle_slot(MultiWork &w, const ptrhash_handle *h, uint32_t next, bool *fresh) {
     const uint32_t mask = w.hcap - 1;
     uint32_t i = (uint32_t)((reinterpret_cast<uintptr_t>(h) >> 4) * 0x9E3779B97F4A7C15ull >> 40) & mask;
@@ -274,13 +292,38 @@ int fill_multi_table_ws(MultiTable *t, const ptrhash_query_desc *descs, int k, u
         b.flags = (bytes ? kBatchBytes : 0u) | (d.handle->params.index_bits == 64 ? kBatchOut64 : 0u);
     }
     uint64_t tiles = 0;
+    double cost = 0;
     for (uint32_t b = 0; b < c; ++b) {
         tb[b] = tiles;
         tiles += (bt[b].nq + tile - 1) / tile;
+        cost += multi_batch_cost(bt[b], mp[bt[b].mphf]);
     }
     t->mphfs = mphfs;
     t->tile = tile;
     t->tiles = tiles;
+    // die x's range starts where the running cost reaches x/8 of the total,
+    // each batch's cost spread evenly over its tiles
+    t->die_first[0] = 0;
+    uint32_t b = 0;
+    double before = 0;  // cost of the batches before b
+    for (uint32_t x = 1; x < kDies; ++x) {
+        const double target = cost * x / kDies;
+        while (b < c) {
+            const double cb = multi_batch_cost(bt[b], mp[bt[b].mphf]);
+            if (before + cb > target) break;
+            before += cb;
+            ++b;
+        }
+        uint64_t first = tiles;
+        if (b < c) {
+            const uint64_t nt = (bt[b].nq + tile - 1) / tile;
+            const double per = multi_batch_cost(bt[b], mp[bt[b].mphf]) / (double)nt;
+            const uint64_t in = (uint64_t)((target - before) / per);
+            first = tb[b] + (in < nt ? in : nt);
+        }
+        t->die_first[x] = first > t->die_first[x - 1] ? first : t->die_first[x - 1];
+    }
+    t->die_first[kDies] = tiles;
     return PTRHASH_OK;
 }
 

@@ -44,21 +44,27 @@ struct MultiBatch {
 };
 enum : uint32_t { kBatchBytes = 1, kBatchOut64 = 2 };
 
+// Compute dies (XCDs) of the device, each with its own L2; the dispatcher
+// hands consecutive workgroups to them in turn (workgroup i to die i mod 8).
+constexpr uint32_t kDies = 8;
+
 // The batches of one multi-MPHF launch, laid out back to back after this
 // header: tile_begin[count] (first global tile of each batch, ascending),
 // batch[count], then mphf[mphfs] (each distinct MPHF once). The kernel's
 // binary search touches only the compact tile_begin array, and a table of
 // many batches over few MPHFs stays small to upload. Batches are grouped by
 // MPHF (in the order the MPHFs first appear), so that a contiguous range of
-// tiles touches few MPHFs.
+// tiles touches few MPHFs. die_first splits the tiles into one contiguous
+// range per die, of about equal estimated work (multi_batch_cost).
 struct MultiTable {
     uint32_t count;  // batches
     uint32_t tile;   // keys per tile the table was numbered with
     uint64_t tiles;  // total tiles
     uint32_t mphfs;  // distinct MPHFs
-    uint32_t pad_[3];
+    uint32_t pad_;
+    uint64_t die_first[kDies + 1];  // die x takes tiles [die_first[x], die_first[x + 1])
 };
-static_assert(sizeof(MultiTable) == 32 && sizeof(MultiBatch) == 48, "multi table layout");
+static_assert(sizeof(MultiTable) == 96 && sizeof(MultiBatch) == 48, "multi table layout");
 
 __host__ __device__ inline uint64_t *multi_tile_begin(MultiTable *t) { return reinterpret_cast<uint64_t *>(t + 1); }
 __host__ __device__ inline const uint64_t *multi_tile_begin(const MultiTable *t) {

@@ -189,18 +189,14 @@ __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict_
                                                      tile_pack + (threadIdx.x / 64u) * 64u);
 }
 
-// Compute dies (XCDs) of the device, each with its own L2; the dispatcher
-// hands consecutive workgroups to them in turn (workgroup i to die i mod 8).
-constexpr uint32_t kXcds = 8;
-
 // Persistent launch over a table of query batches (each against its own
 // resident MPHF). Every batch is cut into tiles of K*blockDim keys (the
 // table records the tile size it was numbered with); tiles are numbered
 // globally (tile_begin is a prefix sum), so batches of any mix of sizes
 // share one launch. The table groups the batches by MPHF, and the workgroups
-// of each die take one contiguous eighth of the tiles, so a die's L2 holds
-// the pilots and remap lines of about an eighth of the MPHFs instead of
-// all of them. The header (batch count, tile count) lives in device memory
+// of each die take one contiguous range of the tiles (an eighth of the
+// estimated work, die_first), so a die's L2 holds the pilots and remap lines
+// of about an eighth of the MPHFs instead of all of them. The header (batch count, tile count) lives in device memory
 // next to the batches, so a captured launch can be replayed over new
 // batches. Remap entries are decoded packed (finish_packed), in 64 u64 of
 // dynamic LDS per wavefront (multi_lds_bytes).
@@ -216,11 +212,11 @@ __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict
     const MultiBatch *__restrict__ bt = multi_batches(table);
     const DevMphf *__restrict__ mp = multi_mphfs(table);
     uint64_t first = blockIdx.x, end = tiles, step = gridDim.x;
-    if (gridDim.x % kXcds == 0) {
-        const uint32_t x = blockIdx.x % kXcds;
-        first = tiles * x / kXcds + blockIdx.x / kXcds;
-        end = tiles * (x + 1) / kXcds;
-        step = gridDim.x / kXcds;
+    if (gridDim.x % kDies == 0) {
+        const uint32_t x = blockIdx.x % kDies;
+        first = table->die_first[x] + blockIdx.x / kDies;
+        end = table->die_first[x + 1];
+        step = gridDim.x / kDies;
     }
     const uint32_t lane = __lane_id();
     for (uint64_t t = first; t < end; t += step) {

@@ -250,8 +250,9 @@ def test_multi_autotuner(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("shape", [(4, 64, 0), (1, 256, 2), (8, 128, 0)])
 def test_tile_split_over_dies_and_batch_search(shape):
-    """The multi launch gives each of the 8 dies a contiguous eighth of the
-    tiles and finds a tile's batch with rounds of 64 parallel reads. Tile
+    """The multi launch gives each of the 8 dies a contiguous range of the
+    tiles (split by estimated work, so some ranges may be empty) and finds a
+    tile's batch with rounds of 64 parallel reads. Tile
     totals around multiples of 8 and below 8, and batch counts around
     powers of 64 (1, 2, 63, 64, 65, 130, 4096), each batch equal to the
     oracle's query of its MPHF, interleaved MPHFs included (the table groups
