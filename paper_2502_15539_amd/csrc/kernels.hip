@@ -12,9 +12,10 @@
 //  - query_pipelined<K>: K keys per lane in a tile of K*blockDim keys; all
 //    K key loads, then all K pilot gathers, are issued before any result is
 //    used (both unconditionally, so that none waits inside a branch). The
-//    rare remap reads stay under their slot >= n branch. Keys and indices
-//    are streamed with non-temporal loads and stores so that they do not
-//    evict pilots from the L2 and MALL.
+//    rare remap reads stay under their slot >= n branch; from 4 keys per
+//    lane on, the wavefront's remapped keys are first packed onto its lanes
+//    (finish_packed). Keys and indices are streamed with non-temporal loads
+//    and stores so that they do not evict pilots from the L2 and MALL.
 //  - query_bytes<K>: the same for packed byte-string keys.
 //  - query_multi: a persistent launch over many batches, each against its
 //    own resident MPHF, described by a table in device memory (stage_in_k
@@ -196,10 +197,11 @@ __global__ void __launch_bounds__(1024) query_bytes_k(const uint8_t *__restrict_
 // share one launch. The table groups the batches by MPHF, and the workgroups
 // of each die take one contiguous range of the tiles (an eighth of the
 // estimated work, die_first), so a die's L2 holds the pilots and remap lines
-// of about an eighth of the MPHFs instead of all of them. The header (batch count, tile count) lives in device memory
-// next to the batches, so a captured launch can be replayed over new
-// batches. Remap entries are decoded packed (finish_packed), in 64 u64 of
-// dynamic LDS per wavefront (multi_lds_bytes).
+// of about an eighth of the MPHFs instead of all of them. The header (batch
+// count, tile count, the dies' ranges) lives in device memory next to the
+// batches, so a captured launch can be replayed over new batches. Remap
+// entries are decoded packed (finish_packed), in 64 u64 of dynamic LDS per
+// wavefront (multi_lds_bytes).
 template <int K>
 __global__ void __launch_bounds__(1024) query_multi(const MultiTable *__restrict__ table) {
     const uint32_t count = table->count;
