@@ -193,7 +193,7 @@ def profiled_traffic(workload, ms, n):
             "read_bytes": t.get("read_bytes"), "write_bytes": t.get("write_bytes"),
             "memory_read_bytes": t.get("memory_read_bytes"),
             "fetch_size_check": (t.get("fetch_size_check") or {}).get("fetch_bytes_scaled"),
-            "source": os.path.relpath(path, ROOT)}
+            "profiled_kernel": t.get("kernel"), "source": os.path.relpath(path, ROOT)}
     return b, info
 
 
